@@ -1,0 +1,271 @@
+/*
+ * ldopf.h - C ABI of the MI355X (gfx950) closed-form ADMM solver for
+ * linearized multi-phase unbalanced optimal power flow.
+ *
+ * The method (Ryu, Byeon, Kim, "A GPU-based Distributed Algorithm for
+ * Linearized Optimal Power Flow in Distribution Systems", PSCC 2024):
+ *   - Section II-A builds the LP  min c'x  s.t.  A x = b,  lo <= x <= hi
+ *     (LP_model) from the network: operational bounds, power balance, the
+ *     voltage-dependent load model, the linearized power flow and the
+ *     objective "sum of generator real power".
+ *   - Section III-A rewrites it as the consensus model OurModel: every
+ *     subsystem s keeps its rows A_s x_s = b_s, a 0-1 matrix B_s selects its
+ *     copies x_s = B_s x of the global variables, and the bounds act only on
+ *     the global vector x.
+ *   - Section III-B gives both ADMM blocks in closed form: the global update
+ *     closed_1 (a clipped average of the copies), the local update closed_2
+ *     (x_s = (1/rho) Abar_s d_s + bbar_s with Abar_s, bbar_s precomputed
+ *     once), and the dual update ADMM-3.
+ *   - Section III-C is the termination test; Algorithm 1 is the whole loop;
+ *     Section V-A gives the decomposition (one subsystem per line and per
+ *     bus, each leaf bus merged into its line), the defaults rho = 100 and
+ *     the initial point.
+ *
+ * Conventions for every call:
+ *   - Host pointers unless a name ends in _device. Inputs are read during the
+ *     call and copied; the library never keeps a caller pointer.
+ *   - Output buffers are caller-allocated; each getter takes a capacity and
+ *     fails with LDOPF_BUFFER_TOO_SMALL (writing nothing) when it is short.
+ *     Sizes come from ldopf_get_sizes.
+ *   - Return value: an ldopf_code. ldopf_last_error_detail() gives a message
+ *     for the most recent failure on the calling thread.
+ *   - A problem handle is used by one host thread at a time.
+ *   - All device work of a handle runs on the HIP stream given at creation
+ *     (NULL: a stream the library creates at default priority).
+ *
+ * Orderings shared by inputs and outputs:
+ *   - Global variables x follow the block order of LP_model: generators
+ *     (p^g, q^g per phase), squared voltages w (per bus, per phase), loads
+ *     (p^b, q^b, p^d, q^d per phase), line flows (p_ij, q_ij, p_ji, q_ji per
+ *     phase); components in input order, phases ascending (a, b, c).
+ *   - Subsystems: one per line in line order (a leaf end bus merged into it),
+ *     then one per non-leaf bus in bus order. A leaf is a non-root bus with
+ *     exactly one incident line.
+ *   - Local copies: subsystem by subsystem, each subsystem's copies sorted by
+ *     global index (gidx ascending).
+ *   - Rows of a line subsystem: per line phase, the two loss rows and the
+ *     voltage-drop row; then, per merged leaf bus, its balance rows (real,
+ *     reactive per phase) and its loads' rows. A bus subsystem: its balance
+ *     rows, then its loads' rows. Wye load rows per phase: p^d model, q^d
+ *     model, p^b = p^d, q^b = q^d. Delta load rows: the three p^d model rows,
+ *     the three q^d model rows, the two sum rows, the four coupling rows.
+ */
+#ifndef LDOPF_H
+#define LDOPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LDOPF_API __attribute__((visibility("default")))
+
+typedef enum ldopf_code {
+    LDOPF_OK = 0,
+    LDOPF_NOT_CONVERGED = 1,           /* max_iter reached; results are valid */
+    LDOPF_INVALID_ARGUMENT = -1,       /* null pointer, bad size or option */
+    LDOPF_INVALID_NETWORK = -2,        /* index out of range, bad phase set, NaN data */
+    LDOPF_INFEASIBLE_BOUNDS = -3,      /* a lower bound above its upper bound */
+    LDOPF_INCONSISTENT_SUBSYSTEM = -4, /* rank-deficient A_s with b_s outside its range */
+    LDOPF_OUT_OF_MEMORY = -5,          /* device allocation failed */
+    LDOPF_DEVICE_ERROR = -6,           /* a HIP call or kernel failed */
+    LDOPF_NUMERICAL = -7,              /* NaN or Inf in the iterate or residuals */
+    LDOPF_BUFFER_TOO_SMALL = -8,       /* output capacity below the needed size */
+    LDOPF_UNSUPPORTED = -9             /* valid request this build does not run */
+} ldopf_code;
+
+typedef enum ldopf_precision {
+    /* every step in FP64 */
+    LDOPF_FP64 = 0,
+    /* global, local and dual updates in FP32 on FP32 copies of the operators;
+     * operator precompute, residual norms and the termination test in FP64 */
+    LDOPF_FP32_MIXED = 1
+} ldopf_precision;
+
+typedef enum ldopf_residual_form {
+    /* Section III-C taken literally: dres = rho * ||x_s - x_s_prev|| and
+     * eps_dual = eps_rel * ||lambda|| over all local copies */
+    LDOPF_RESIDUAL_PAPER = 0,
+    /* textbook form with sum_s B_s' applied before the norm (oracle only in
+     * this build; the device path returns LDOPF_UNSUPPORTED) */
+    LDOPF_RESIDUAL_AGGREGATED = 1
+} ldopf_residual_form;
+
+/*
+ * Network data (nomenclature table of Section II). Structure of arrays,
+ * caller-owned, copied by ldopf_create. Per-phase arrays are [count x 3]
+ * row-major with columns a, b, c; 3x3 matrices are [count x 9] row-major.
+ * Phase sets are bitmasks a=1, b=2, c=4. Entries for phases a component does
+ * not carry are ignored. Pointers marked "nullable" take the stated default.
+ */
+typedef struct ldopf_network {
+    int32_t n_bus, n_line, n_load, n_gen;
+    int32_t root;                 /* substation bus (never a leaf) */
+    const uint8_t* bus_phases;    /* [n_bus] */
+    const double* bus_wlo;        /* [n_bus x 3] squared-voltage bounds; nullable: -inf */
+    const double* bus_whi;        /* nullable: +inf */
+    const double* bus_gsh;        /* shunt conductance g^sh; nullable: 0 */
+    const double* bus_bsh;        /* shunt susceptance b^sh; nullable: 0 */
+    const int32_t* line_from;     /* [n_line] bus i of line (e, i, j) */
+    const int32_t* line_to;       /* [n_line] bus j */
+    const uint8_t* line_phases;   /* [n_line], subset of both end buses' phases */
+    const double* line_r;         /* [n_line x 9] series resistance, per unit */
+    const double* line_x;         /* [n_line x 9] series reactance, per unit */
+    const double* line_gs_from;   /* [n_line x 3] g^s at the i end; nullable: 0 */
+    const double* line_bs_from;   /* b^s at the i end; nullable: 0 */
+    const double* line_gs_to;     /* g^s at the j end; nullable: 0 */
+    const double* line_bs_to;     /* b^s at the j end; nullable: 0 */
+    const double* line_tau;       /* [n_line x 3] tap ratio; nullable: 1 */
+    const double* line_plo;       /* [n_line x 3] bounds on p at both ends; nullable: -inf */
+    const double* line_phi;       /* nullable: +inf */
+    const double* line_qlo;       /* bounds on q at both ends; nullable: -inf */
+    const double* line_qhi;       /* nullable: +inf */
+    const int32_t* load_bus;      /* [n_load] */
+    const uint8_t* load_phases;   /* [n_load], subset of the bus's phases */
+    const uint8_t* load_conn;     /* [n_load] 0 wye, 1 delta (three-phase only); nullable: wye */
+    const double* load_a;         /* [n_load x 3] reference real power a */
+    const double* load_b;         /* reference reactive power b */
+    const double* load_alpha;     /* load-type exponent alpha; nullable: 0 */
+    const double* load_beta;      /* load-type exponent beta; nullable: 0 */
+    const int32_t* gen_bus;       /* [n_gen] */
+    const uint8_t* gen_phases;    /* [n_gen], subset of the bus's phases */
+    const double* gen_plo;        /* [n_gen x 3]; nullable: -inf */
+    const double* gen_phi;        /* nullable: +inf */
+    const double* gen_qlo;        /* nullable: -inf */
+    const double* gen_qhi;        /* nullable: +inf */
+    const double* gen_cost_p;     /* objective coefficient of p^g; nullable: 1 */
+    const double* gen_cost_q;     /* objective coefficient of q^g; nullable: 0 */
+} ldopf_network;
+
+typedef struct ldopf_options {
+    double rho;              /* penalty of the augmented Lagrangian; default 100 (Section V-A) */
+    double eps_rel;          /* relative tolerance of the termination test; default 1e-4 */
+    double eps_abs;          /* absolute term sqrt(dim) * eps_abs added to both tolerances; default 0 */
+    int64_t max_iter;        /* sweep limit; default 1e6 */
+    int32_t precision;       /* ldopf_precision; default LDOPF_FP64 */
+    int32_t residual_form;   /* ldopf_residual_form; default LDOPF_RESIDUAL_PAPER */
+    int32_t check_termination; /* 1 (default): stop at the test; 0: run exactly max_iter sweeps */
+    int32_t history;         /* 1 (default): record pres, dres, eps_prim, eps_dual per sweep */
+    int32_t rows_per_part;   /* tuning: local copies per workgroup; 0 = automatic */
+    int32_t block_threads;   /* tuning: threads per workgroup (64..1024, multiple of 64); 0 = automatic */
+    int32_t reserved[6];     /* must be zero */
+} ldopf_options;
+
+typedef struct ldopf_sizes {
+    int64_t n;          /* global variables */
+    int64_t n_sub;      /* subsystems S */
+    int64_t n_local;    /* local copies, sum of n_s */
+    int64_t sum_m;      /* sum of m_s */
+    int64_t op_words;   /* sum of n_s * n_s (dense operators, ldopf_get_operators) */
+    int64_t rank_words; /* sum of n_s * K_s, K_s = min(rank_s, n_s - rank_s): the sweep's operator */
+    int32_t max_n, max_m;
+    int32_t n_parts;    /* workgroups of the persistent sweep */
+    int32_t block_threads;
+    int64_t lds_bytes;  /* LDS per workgroup of the sweep */
+} ldopf_sizes;
+
+typedef struct ldopf_status {
+    int64_t iterations;   /* completed sweeps of this solve call */
+    int32_t converged;    /* termination test met */
+    int32_t code;         /* ldopf_code of the solve */
+    double pres, dres, eps_prim, eps_dual; /* last sweep */
+    double sweep_ms;      /* device time of the sweep kernel (HIP events on the handle's stream) */
+    double precompute_ms; /* device time of the operator precompute at creation */
+} ldopf_status;
+
+typedef struct ldopf_problem ldopf_problem;
+
+LDOPF_API const char* ldopf_error_string(int code);
+LDOPF_API const char* ldopf_last_error_detail(void);
+LDOPF_API void ldopf_default_options(ldopf_options* opts);
+
+/*
+ * Host-only: assemble and decompose a network without touching the GPU.
+ * Writes the consensus LP of OurModel: c, lo, hi and the starting value of
+ * each global variable [n]; per subsystem n_s, m_s [S]; A (all A_s blocks,
+ * row-major, concatenated), b (concatenated), gidx (all copies, concatenated).
+ * Call with every output pointer NULL to get the sizes only:
+ *   sizes[0] = n, [1] = S, [2] = N_loc, [3] = total A words, [4] = total rows.
+ */
+LDOPF_API int ldopf_describe_network(const ldopf_network* net, int64_t sizes[5],
+                                     double* c, double* lo, double* hi, double* x_init,
+                                     int32_t* n_s, int32_t* m_s, double* A, double* b,
+                                     int64_t* gidx);
+
+/*
+ * Assemble, decompose, upload and precompute Abar_s, bbar_s in FP64 on the
+ * device (Algorithm 1 precomputation; Section III-B). The problem starts at
+ * the initial point of Section V-A (lambda = 0; copies of a squared voltage
+ * at 1, of a variable with two finite bounds at their midpoint, others at 0
+ * clipped into the box). stream: a hipStream_t or NULL.
+ */
+LDOPF_API int ldopf_create(const ldopf_network* net, const ldopf_options* opts, void* stream,
+                           ldopf_problem** out);
+
+/*
+ * The same from the consensus LP directly (OurModel): n globals with c, lo,
+ * hi; x_init [n] nullable (then: midpoint of finite boxes, else 0 clipped);
+ * S subsystems with sizes n_s, m_s; A: the row-major m_s x n_s blocks
+ * concatenated; b: concatenated; gidx: each subsystem's global indices,
+ * strictly ascending within a subsystem (B_s has row sums 1 and column sums
+ * <= 1). Every global variable needs at least one copy.
+ */
+LDOPF_API int ldopf_create_lp(int64_t n, const double* c, const double* lo, const double* hi,
+                              const double* x_init, int64_t n_sub, const int32_t* n_s,
+                              const int32_t* m_s, const double* A, const double* b,
+                              const int64_t* gidx, const ldopf_options* opts, void* stream,
+                              ldopf_problem** out);
+
+LDOPF_API int ldopf_destroy(ldopf_problem* h);
+LDOPF_API int ldopf_get_sizes(const ldopf_problem* h, ldopf_sizes* out);
+
+/* Replace rho, eps_rel, eps_abs, max_iter, check_termination, history for
+ * later solves. Abar_s, bbar_s do not depend on rho, so nothing is
+ * recomputed. precision and tuning fields must equal the creation values. */
+LDOPF_API int ldopf_set_options(ldopf_problem* h, const ldopf_options* opts);
+
+/*
+ * Run ADMM sweeps (Algorithm 1: global update closed_1, local update
+ * closed_2, dual update ADMM-3, termination test of Section III-C) from the
+ * handle's current state until the test holds or max_iter sweeps ran; the
+ * state then holds the last sweep's x, x_s, lambda. Blocks until done.
+ * Returns LDOPF_OK, LDOPF_NOT_CONVERGED, LDOPF_NUMERICAL or an error.
+ */
+LDOPF_API int ldopf_solve(ldopf_problem* h, ldopf_status* status);
+
+/* Back to the initial point of Section V-A. */
+LDOPF_API int ldopf_reset(ldopf_problem* h);
+
+/* Continue from a given state: x_s and lambda [N_loc] in local-copy order.
+ * A following ldopf_solve resumes exactly as if the sweeps had not stopped. */
+LDOPF_API int ldopf_warm_start(ldopf_problem* h, const double* xs, const double* lam, int64_t n_local);
+
+/* Global x [n] of the last sweep (NaN before the first sweep). */
+LDOPF_API int ldopf_get_global(const ldopf_problem* h, double* x, int64_t cap);
+/* Local copies x_s and duals lambda [N_loc]; either pointer may be NULL. */
+LDOPF_API int ldopf_get_local(const ldopf_problem* h, double* xs, double* lam, int64_t cap);
+/* gidx [N_loc] and subsystem offsets [S+1] of the local-copy order. */
+LDOPF_API int ldopf_get_structure(const ldopf_problem* h, int64_t* gidx, int64_t cap_local,
+                                  int64_t* sub_off, int64_t cap_sub);
+/* Residual history of the last solve: [len x 4] = pres, dres, eps_prim, eps_dual. */
+LDOPF_API int ldopf_get_history(const ldopf_problem* h, double* hist, int64_t cap_rows, int64_t* len);
+/* Precomputed operators in FP64: dense Abar_s blocks [op_words] row-major,
+ * bbar [N_loc], numerical rank of each A_s [S]; any pointer may be NULL. */
+LDOPF_API int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t cap_abar,
+                                  double* bbar, int64_t cap_bbar, int32_t* rank, int64_t cap_rank);
+/* c'x at the last sweep's global x. */
+LDOPF_API int ldopf_objective(const ldopf_problem* h, double* f);
+
+/* Device-pointer getters for caller-allocated device buffers (for example
+ * torch tensors); enqueued on the handle's stream, which the caller then
+ * orders against its own work. */
+LDOPF_API int ldopf_get_global_device(const ldopf_problem* h, double* x_device, int64_t cap);
+LDOPF_API int ldopf_get_local_device(const ldopf_problem* h, double* xs_device, double* lam_device,
+                                     int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDOPF_H */

@@ -1,0 +1,664 @@
+// C ABI of libldopf: validation, ownership, device buffers and the calls of
+// include/ldopf.h. The arithmetic of the method runs in device.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace ldopf {
+
+namespace {
+thread_local std::string g_detail;
+}
+
+void fail(int code, const std::string& detail) { throw Error{code, detail}; }
+
+static void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? LDOPF_OUT_OF_MEMORY : LDOPF_DEVICE_ERROR;
+    fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Owning device allocation.
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t count = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        count = 0;
+    }
+    void alloc(size_t n, const char* what) {
+        release();
+        const size_t bytes = std::max<size_t>(1, n) * sizeof(T);
+        hip_check(hipMalloc(reinterpret_cast<void**>(&p), bytes), what);
+        count = n;
+    }
+    void upload(const std::vector<T>& v, hipStream_t s, const char* what) {
+        alloc(v.size(), what);
+        if (!v.empty()) hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), what);
+    }
+};
+
+}  // namespace ldopf
+
+using namespace ldopf;
+
+struct ldopf_problem {
+    ConsensusLP lp;
+    ldopf_options opts{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool fp32 = false;
+    Plan plan;
+    std::vector<int32_t> rank;
+    double precompute_ms = 0.0;
+    double last_sweep_ms = 0.0;
+    int64_t hist_len = 0;
+    bool have_x = false;
+    uint64_t spin_limit = 0;
+
+    DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart;
+    DevBuf<int32_t> ns, ms, rank_d, flags;
+    DevBuf<int64_t> a_off, row_off, loc_off, basis_off;
+    DevBuf<PartInfo> parts;
+    DevBuf<SubMeta> subs;
+    DevBuf<int32_t> row_canon, var_gid, var_slot, var_slot_lo, var_slot_hi;
+    DevBuf<uint16_t> row_lvar, row_sub, var_copy_off, var_copy_rows, tk_sub;
+    DevBuf<uint8_t> var_writer;
+    DevBuf<unsigned char> bpart;
+    DevBuf<unsigned> bar;
+    DevBuf<SweepStatus> st;
+
+    ~ldopf_problem() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+template <typename F>
+int guard(F&& f) {
+    try {
+        f();
+        return LDOPF_OK;
+    } catch (const Error& e) {
+        g_detail = e.detail;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_detail = "host allocation failed";
+        return LDOPF_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        g_detail = e.what();
+        return LDOPF_DEVICE_ERROR;
+    }
+}
+
+void check_options(const ldopf_options& o) {
+    if (!(o.rho > 0.0) || !std::isfinite(o.rho)) fail(LDOPF_INVALID_ARGUMENT, "rho must be positive and finite");
+    if (!(o.eps_rel >= 0.0) || !std::isfinite(o.eps_rel)) fail(LDOPF_INVALID_ARGUMENT, "eps_rel must be >= 0");
+    if (!(o.eps_abs >= 0.0) || !std::isfinite(o.eps_abs)) fail(LDOPF_INVALID_ARGUMENT, "eps_abs must be >= 0");
+    if (o.max_iter < 0) fail(LDOPF_INVALID_ARGUMENT, "max_iter must be >= 0");
+    if (o.precision != LDOPF_FP64 && o.precision != LDOPF_FP32_MIXED) fail(LDOPF_INVALID_ARGUMENT, "unknown precision");
+    if (o.residual_form == LDOPF_RESIDUAL_AGGREGATED)
+        fail(LDOPF_UNSUPPORTED, "the aggregated residual form is not implemented on the device");
+    if (o.residual_form != LDOPF_RESIDUAL_PAPER) fail(LDOPF_INVALID_ARGUMENT, "unknown residual form");
+    if (o.check_termination != 0 && o.check_termination != 1) fail(LDOPF_INVALID_ARGUMENT, "check_termination must be 0 or 1");
+    if (o.history != 0 && o.history != 1) fail(LDOPF_INVALID_ARGUMENT, "history must be 0 or 1");
+    if (o.rows_per_part < 0) fail(LDOPF_INVALID_ARGUMENT, "rows_per_part must be >= 0");
+    if (o.block_threads != 0 && (o.block_threads < 64 || o.block_threads > 1024 || o.block_threads % 64))
+        fail(LDOPF_INVALID_ARGUMENT, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
+    for (int r : o.reserved)
+        if (r != 0) fail(LDOPF_INVALID_ARGUMENT, "reserved option fields must be zero");
+}
+
+void init_state(ldopf_problem& h) {
+    const ConsensusLP& lp = h.lp;
+    std::vector<double> xs(lp.gidx.size()), lam(lp.gidx.size(), 0.0), x(lp.n, NAN);
+    for (size_t k = 0; k < lp.gidx.size(); ++k) xs[k] = lp.x_init[lp.gidx[k]];
+    hip_check(hipMemcpyAsync(h.xs.p, xs.data(), xs.size() * 8, hipMemcpyHostToDevice, h.stream), "upload x_s");
+    hip_check(hipMemcpyAsync(h.lam.p, lam.data(), lam.size() * 8, hipMemcpyHostToDevice, h.stream), "upload lambda");
+    hip_check(hipMemcpyAsync(h.x.p, x.data(), x.size() * 8, hipMemcpyHostToDevice, h.stream), "upload x");
+    hip_check(hipStreamSynchronize(h.stream), "initial state");
+    h.have_x = false;
+    h.hist_len = 0;
+}
+
+// Everything after the host LP exists: device precompute, plan, buffers.
+void build_device(ldopf_problem& h) {
+    ConsensusLP& lp = h.lp;
+    hipStream_t s = h.stream;
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    int cus = 0, coop = 0, lds_optin = 0, clock_khz = 0;
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+    hip_check(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev), "device attribute");
+    hip_check(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, dev), "device attribute");
+    hip_check(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev), "device attribute");
+    if (!coop) fail(LDOPF_UNSUPPORTED, "the device does not support cooperative launches");
+    if (lds_optin <= 0) hip_check(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device attribute");
+    // a barrier wait longer than 5 s means the launch is broken
+    h.spin_limit = uint64_t(std::max(clock_khz, 1000)) * 1000ull * 5ull;
+
+    for (int32_t n : lp.ns)
+        if (n > 255) fail(LDOPF_UNSUPPORTED, "subsystems with more than 255 variables are not supported on the device");
+    const int64_t S = lp.S;
+    std::vector<int64_t> boff(S + 1, 0);
+    for (int64_t i = 0; i < S; ++i) boff[i + 1] = boff[i] + int64_t(lp.ns[i]) * lp.ns[i];
+
+    h.A.upload(lp.A, s, "upload A");
+    h.b.upload(lp.b, s, "upload b");
+    h.ns.upload(lp.ns, s, "upload n_s");
+    h.ms.upload(lp.ms, s, "upload m_s");
+    h.a_off.upload(lp.a_off, s, "upload offsets");
+    h.row_off.upload(lp.row_off, s, "upload offsets");
+    h.loc_off.upload(lp.loc_off, s, "upload offsets");
+    h.basis_off.upload(boff, s, "upload offsets");
+    h.basis.alloc(boff[S], "basis");
+    h.abar.alloc(boff[S], "abar");
+    h.bbar.alloc(lp.gidx.size(), "bbar");
+    h.rank_d.alloc(S, "rank");
+    h.flags.alloc(S, "flags");
+
+    PrecomputeArgs pa{};
+    pa.S = S;
+    pa.ns = h.ns.p;
+    pa.ms = h.ms.p;
+    pa.a_off = h.a_off.p;
+    pa.row_off = h.row_off.p;
+    pa.loc_off = h.loc_off.p;
+    pa.basis_off = h.basis_off.p;
+    pa.A = h.A.p;
+    pa.b = h.b.p;
+    pa.basis = h.basis.p;
+    pa.abar = h.abar.p;
+    pa.bbar = h.bbar.p;
+    pa.rank = h.rank_d.p;
+    pa.flags = h.flags.p;
+    pa.tol_dep = 1e-10;
+    pa.tol_rhs = 1e-9;
+    hip_check(hipEventRecord(h.ev0, s), "event");
+    hip_check(launch_precompute(pa, s), "precompute launch");
+    hip_check(hipEventRecord(h.ev1, s), "event");
+    h.rank.resize(S);
+    std::vector<int32_t> flags(S);
+    hip_check(hipMemcpyAsync(h.rank.data(), h.rank_d.p, S * 4, hipMemcpyDeviceToHost, s), "download ranks");
+    hip_check(hipMemcpyAsync(flags.data(), h.flags.p, S * 4, hipMemcpyDeviceToHost, s), "download flags");
+    hip_check(hipStreamSynchronize(s), "precompute");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, h.ev0, h.ev1), "event time");
+    h.precompute_ms = ms;
+    for (int64_t i = 0; i < S; ++i)
+        if (flags[i]) fail(LDOPF_INCONSISTENT_SUBSYSTEM, "subsystem " + std::to_string(i) + ": dependent rows with inconsistent right-hand side");
+    // the rows of A_s are no longer needed on the device
+    h.A.release();
+    h.b.release();
+
+    h.plan = make_plan(lp, h.rank, h.fp32, h.opts.rows_per_part, h.opts.block_threads, cus, lds_optin);
+    const Plan& pl = h.plan;
+    hip_check(prepare_sweep(h.fp32, size_t(pl.lds_bytes)), "sweep LDS attribute");
+    int per_cu = 0;
+    hip_check(sweep_occupancy(h.fp32, pl.block_threads, size_t(pl.lds_bytes), &per_cu), "sweep occupancy");
+    if (int64_t(per_cu) * cus < pl.n_parts)
+        fail(LDOPF_UNSUPPORTED, "the sweep's " + std::to_string(pl.n_parts) + " workgroups cannot be co-resident (" +
+                                    std::to_string(per_cu) + " per CU, " + std::to_string(cus) + " CUs)");
+
+    h.parts.upload(pl.parts, s, "upload plan");
+    h.subs.upload(pl.subs, s, "upload plan");
+    h.row_canon.upload(pl.row_canon, s, "upload plan");
+    h.row_lvar.upload(pl.row_lvar, s, "upload plan");
+    h.row_sub.upload(pl.row_sub, s, "upload plan");
+    h.var_gid.upload(pl.var_gid, s, "upload plan");
+    h.var_slot.upload(pl.var_slot, s, "upload plan");
+    h.var_slot_lo.upload(pl.var_slot_lo, s, "upload plan");
+    h.var_slot_hi.upload(pl.var_slot_hi, s, "upload plan");
+    h.var_writer.upload(pl.var_writer, s, "upload plan");
+    h.var_copy_off.upload(pl.var_copy_off, s, "upload plan");
+    h.var_copy_rows.upload(pl.var_copy_rows, s, "upload plan");
+    h.tk_sub.upload(pl.tk_sub, s, "upload plan");
+
+    std::vector<double> cnt(lp.n, 0.0);
+    for (int64_t g : lp.gidx) cnt[g] += 1.0;
+    h.c.upload(lp.c, s, "upload c");
+    h.lo.upload(lp.lo, s, "upload lo");
+    h.hi.upload(lp.hi, s, "upload hi");
+    h.cnt.upload(cnt, s, "upload counts");
+    h.xs.alloc(lp.gidx.size(), "x_s");
+    h.lam.alloc(lp.gidx.size(), "lambda");
+    h.x.alloc(lp.n, "x");
+    h.bpart.alloc(size_t(2) * std::max(pl.n_slots, 1) * (h.fp32 ? 4 : 8), "boundary slots");
+    h.rpart.alloc(size_t(2) * pl.n_parts * 8, "residual slots");
+    h.bar.alloc(128, "barrier");
+    h.st.alloc(1, "status");
+    init_state(h);
+}
+
+template <typename T>
+SweepArgs<T> sweep_args(ldopf_problem& h) {
+    SweepArgs<T> a{};
+    a.parts = h.parts.p;
+    a.subs = h.subs.p;
+    a.row_canon = h.row_canon.p;
+    a.row_lvar = h.row_lvar.p;
+    a.row_sub = h.row_sub.p;
+    a.var_gid = h.var_gid.p;
+    a.var_slot = h.var_slot.p;
+    a.var_slot_lo = h.var_slot_lo.p;
+    a.var_slot_hi = h.var_slot_hi.p;
+    a.var_writer = h.var_writer.p;
+    a.var_copy_off = h.var_copy_off.p;
+    a.var_copy_rows = h.var_copy_rows.p;
+    a.tk_sub = h.tk_sub.p;
+    a.basis = h.basis.p;
+    a.bbar = h.bbar.p;
+    a.c = h.c.p;
+    a.lo = h.lo.p;
+    a.hi = h.hi.p;
+    a.cnt = h.cnt.p;
+    a.xs = h.xs.p;
+    a.lam = h.lam.p;
+    a.x = h.x.p;
+    a.bpart = reinterpret_cast<T*>(h.bpart.p);
+    a.rpart = h.rpart.p;
+    a.bar = h.bar.p;
+    a.hist = h.hist.p;
+    a.hist_cap = h.opts.history ? int64_t(h.hist.count / 4) : 0;
+    a.st = h.st.p;
+    a.rho = h.opts.rho;
+    a.eps_rel = h.opts.eps_rel;
+    a.eps_abs = h.opts.eps_abs;
+    a.max_iter = h.opts.max_iter;
+    a.nloc = int64_t(h.lp.gidx.size());
+    a.n_slots = h.plan.n_slots;
+    a.check = h.opts.check_termination;
+    a.P = h.plan.n_parts;
+    a.spin_limit = h.spin_limit;
+    return a;
+}
+
+ldopf_problem* new_problem(const ldopf_options* opts, void* stream) {
+    ldopf_options o;
+    ldopf_default_options(&o);
+    if (opts) o = *opts;
+    check_options(o);
+    auto* h = new ldopf_problem();
+    h->opts = o;
+    h->fp32 = o.precision == LDOPF_FP32_MIXED;
+    try {
+        if (stream) {
+            h->stream = static_cast<hipStream_t>(stream);
+        } else {
+            hip_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "stream");
+            h->own_stream = true;
+        }
+        hip_check(hipEventCreate(&h->ev0), "event");
+        hip_check(hipEventCreate(&h->ev1), "event");
+    } catch (...) {
+        delete h;
+        throw;
+    }
+    return h;
+}
+
+void need(const void* p, const char* what) {
+    if (!p) fail(LDOPF_INVALID_ARGUMENT, std::string(what) + " must not be NULL");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ldopf_error_string(int code) {
+    switch (code) {
+        case LDOPF_OK: return "ok";
+        case LDOPF_NOT_CONVERGED: return "not converged within max_iter";
+        case LDOPF_INVALID_ARGUMENT: return "invalid argument";
+        case LDOPF_INVALID_NETWORK: return "invalid network";
+        case LDOPF_INFEASIBLE_BOUNDS: return "infeasible bounds";
+        case LDOPF_INCONSISTENT_SUBSYSTEM: return "inconsistent subsystem";
+        case LDOPF_OUT_OF_MEMORY: return "out of memory";
+        case LDOPF_DEVICE_ERROR: return "device error";
+        case LDOPF_NUMERICAL: return "numerical failure (NaN or Inf)";
+        case LDOPF_BUFFER_TOO_SMALL: return "buffer too small";
+        case LDOPF_UNSUPPORTED: return "unsupported";
+        default: return "unknown code";
+    }
+}
+
+const char* ldopf_last_error_detail(void) { return g_detail.c_str(); }
+
+void ldopf_default_options(ldopf_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rho = 100.0;
+    o->eps_rel = 1e-4;
+    o->eps_abs = 0.0;
+    o->max_iter = 1000000;
+    o->precision = LDOPF_FP64;
+    o->residual_form = LDOPF_RESIDUAL_PAPER;
+    o->check_termination = 1;
+    o->history = 1;
+}
+
+int ldopf_describe_network(const ldopf_network* net, int64_t sizes[5], double* c, double* lo, double* hi,
+                           double* x_init, int32_t* n_s, int32_t* m_s, double* A, double* b, int64_t* gidx) {
+    return guard([&] {
+        need(net, "net");
+        need(sizes, "sizes");
+        ConsensusLP lp = assemble_network(*net);
+        sizes[0] = lp.n;
+        sizes[1] = lp.S;
+        sizes[2] = int64_t(lp.gidx.size());
+        sizes[3] = int64_t(lp.A.size());
+        sizes[4] = int64_t(lp.b.size());
+        auto put = [](auto* dst, const auto& v) {
+            if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+        };
+        put(c, lp.c);
+        put(lo, lp.lo);
+        put(hi, lp.hi);
+        put(x_init, lp.x_init);
+        put(n_s, lp.ns);
+        put(m_s, lp.ms);
+        put(A, lp.A);
+        put(b, lp.b);
+        put(gidx, lp.gidx);
+    });
+}
+
+int ldopf_create(const ldopf_network* net, const ldopf_options* opts, void* stream, ldopf_problem** out) {
+    return guard([&] {
+        need(net, "net");
+        need(out, "out");
+        *out = nullptr;
+        ConsensusLP lp = assemble_network(*net);
+        ldopf_problem* h = new_problem(opts, stream);
+        try {
+            h->lp = std::move(lp);
+            build_device(*h);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+int ldopf_create_lp(int64_t n, const double* c, const double* lo, const double* hi, const double* x_init,
+                    int64_t n_sub, const int32_t* n_s, const int32_t* m_s, const double* A, const double* b,
+                    const int64_t* gidx, const ldopf_options* opts, void* stream, ldopf_problem** out) {
+    return guard([&] {
+        need(out, "out");
+        *out = nullptr;
+        if (n < 1 || n_sub < 1) fail(LDOPF_INVALID_ARGUMENT, "n and n_sub must be >= 1");
+        need(c, "c");
+        need(lo, "lo");
+        need(hi, "hi");
+        need(n_s, "n_s");
+        need(m_s, "m_s");
+        need(gidx, "gidx");
+        ConsensusLP lp;
+        lp.n = n;
+        lp.c.assign(c, c + n);
+        lp.lo.assign(lo, lo + n);
+        lp.hi.assign(hi, hi + n);
+        if (x_init) lp.x_init.assign(x_init, x_init + n);
+        lp.S = n_sub;
+        lp.ns.assign(n_s, n_s + n_sub);
+        lp.ms.assign(m_s, m_s + n_sub);
+        int64_t nloc = 0, words = 0, rows = 0;
+        for (int64_t s = 0; s < n_sub; ++s) {
+            if (n_s[s] < 1 || m_s[s] < 0) fail(LDOPF_INVALID_ARGUMENT, "n_s must be >= 1 and m_s >= 0");
+            nloc += n_s[s];
+            rows += m_s[s];
+            words += int64_t(n_s[s]) * m_s[s];
+        }
+        if (words > 0) need(A, "A");
+        if (rows > 0) need(b, "b");
+        if (words > 0) lp.A.assign(A, A + words);
+        if (rows > 0) lp.b.assign(b, b + rows);
+        lp.gidx.assign(gidx, gidx + nloc);
+        finish_lp(lp);
+        ldopf_problem* h = new_problem(opts, stream);
+        try {
+            h->lp = std::move(lp);
+            build_device(*h);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+int ldopf_destroy(ldopf_problem* h) {
+    return guard([&] { delete h; });
+}
+
+int ldopf_get_sizes(const ldopf_problem* h, ldopf_sizes* o) {
+    return guard([&] {
+        need(h, "handle");
+        need(o, "out");
+        std::memset(o, 0, sizeof(*o));
+        o->n = h->lp.n;
+        o->n_sub = h->lp.S;
+        o->n_local = int64_t(h->lp.gidx.size());
+        o->sum_m = int64_t(h->lp.b.size());
+        int64_t ow = 0;
+        int32_t mn = 0, mm = 0;
+        for (int64_t s = 0; s < h->lp.S; ++s) {
+            ow += int64_t(h->lp.ns[s]) * h->lp.ns[s];
+            mn = std::max(mn, h->lp.ns[s]);
+            mm = std::max(mm, h->lp.ms[s]);
+        }
+        o->op_words = ow;
+        o->rank_words = h->plan.rank_words;
+        o->max_n = mn;
+        o->max_m = mm;
+        o->n_parts = h->plan.n_parts;
+        o->block_threads = h->plan.block_threads;
+        o->lds_bytes = h->plan.lds_bytes;
+    });
+}
+
+int ldopf_set_options(ldopf_problem* h, const ldopf_options* opts) {
+    return guard([&] {
+        need(h, "handle");
+        need(opts, "opts");
+        check_options(*opts);
+        if (opts->precision != h->opts.precision || opts->rows_per_part != h->opts.rows_per_part ||
+            opts->block_threads != h->opts.block_threads)
+            fail(LDOPF_INVALID_ARGUMENT, "precision and tuning fields are fixed at creation");
+        h->opts = *opts;
+    });
+}
+
+int ldopf_solve(ldopf_problem* h, ldopf_status* status) {
+    int code = LDOPF_OK;
+    const int rc = guard([&] {
+        need(h, "handle");
+        const int64_t want = h->opts.history ? std::min<int64_t>(std::max<int64_t>(h->opts.max_iter, 1), int64_t(1) << 22) : 1;
+        if (int64_t(h->hist.count) < want * 4) h->hist.alloc(size_t(want) * 4, "history");
+        hipError_t e;
+        hip_check(hipEventRecord(h->ev0, h->stream), "event");
+        if (h->fp32) {
+            e = launch_sweep(sweep_args<float>(*h), h->plan.n_parts, h->plan.block_threads, size_t(h->plan.lds_bytes), h->stream);
+        } else {
+            e = launch_sweep(sweep_args<double>(*h), h->plan.n_parts, h->plan.block_threads, size_t(h->plan.lds_bytes), h->stream);
+        }
+        hip_check(e, "sweep launch");
+        hip_check(hipEventRecord(h->ev1, h->stream), "event");
+        SweepStatus st{};
+        hip_check(hipMemcpyAsync(&st, h->st.p, sizeof(st), hipMemcpyDeviceToHost, h->stream), "download status");
+        hip_check(hipStreamSynchronize(h->stream), "sweep");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1), "event time");
+        h->last_sweep_ms = ms;
+        h->hist_len = h->opts.history ? std::min<int64_t>(st.iters, int64_t(h->hist.count / 4)) : 0;
+        if (st.iters > 0) h->have_x = true;
+        if (st.flags & 1) fail(LDOPF_DEVICE_ERROR, "grid barrier wait timed out in the sweep kernel");
+        if (status) {
+            status->iterations = st.iters;
+            status->converged = st.converged;
+            status->pres = st.pres;
+            status->dres = st.dres;
+            status->eps_prim = st.eps_p;
+            status->eps_dual = st.eps_d;
+            status->sweep_ms = ms;
+            status->precompute_ms = h->precompute_ms;
+        }
+        if (st.flags & 2) {
+            code = LDOPF_NUMERICAL;
+            g_detail = "non-finite residual sums";
+        } else if (h->opts.check_termination && !st.converged) {
+            code = LDOPF_NOT_CONVERGED;
+        }
+    });
+    if (status) status->code = rc != LDOPF_OK ? rc : code;
+    return rc != LDOPF_OK ? rc : code;
+}
+
+int ldopf_reset(ldopf_problem* h) {
+    return guard([&] {
+        need(h, "handle");
+        init_state(*h);
+    });
+}
+
+int ldopf_warm_start(ldopf_problem* h, const double* xs, const double* lam, int64_t n_local) {
+    return guard([&] {
+        need(h, "handle");
+        need(xs, "xs");
+        need(lam, "lam");
+        if (n_local != int64_t(h->lp.gidx.size())) fail(LDOPF_INVALID_ARGUMENT, "n_local does not match the problem");
+        for (int64_t k = 0; k < n_local; ++k)
+            if (!std::isfinite(xs[k]) || !std::isfinite(lam[k])) fail(LDOPF_INVALID_ARGUMENT, "non-finite warm-start value");
+        hip_check(hipMemcpyAsync(h->xs.p, xs, n_local * 8, hipMemcpyHostToDevice, h->stream), "upload x_s");
+        hip_check(hipMemcpyAsync(h->lam.p, lam, n_local * 8, hipMemcpyHostToDevice, h->stream), "upload lambda");
+        hip_check(hipStreamSynchronize(h->stream), "warm start");
+        h->hist_len = 0;
+    });
+}
+
+int ldopf_get_global(const ldopf_problem* h, double* x, int64_t cap) {
+    return guard([&] {
+        need(h, "handle");
+        need(x, "x");
+        if (cap < h->lp.n) fail(LDOPF_BUFFER_TOO_SMALL, "x needs n entries");
+        hip_check(hipMemcpyAsync(x, h->x.p, h->lp.n * 8, hipMemcpyDeviceToHost, h->stream), "download x");
+        hip_check(hipStreamSynchronize(h->stream), "download x");
+    });
+}
+
+int ldopf_get_local(const ldopf_problem* h, double* xs, double* lam, int64_t cap) {
+    return guard([&] {
+        need(h, "handle");
+        const int64_t nl = int64_t(h->lp.gidx.size());
+        if (cap < nl) fail(LDOPF_BUFFER_TOO_SMALL, "x_s and lambda need N_loc entries");
+        if (xs) hip_check(hipMemcpyAsync(xs, h->xs.p, nl * 8, hipMemcpyDeviceToHost, h->stream), "download x_s");
+        if (lam) hip_check(hipMemcpyAsync(lam, h->lam.p, nl * 8, hipMemcpyDeviceToHost, h->stream), "download lambda");
+        hip_check(hipStreamSynchronize(h->stream), "download state");
+    });
+}
+
+int ldopf_get_structure(const ldopf_problem* h, int64_t* gidx, int64_t cap_local, int64_t* sub_off, int64_t cap_sub) {
+    return guard([&] {
+        need(h, "handle");
+        if (gidx) {
+            if (cap_local < int64_t(h->lp.gidx.size())) fail(LDOPF_BUFFER_TOO_SMALL, "gidx needs N_loc entries");
+            std::memcpy(gidx, h->lp.gidx.data(), h->lp.gidx.size() * 8);
+        }
+        if (sub_off) {
+            if (cap_sub < h->lp.S + 1) fail(LDOPF_BUFFER_TOO_SMALL, "sub_off needs S + 1 entries");
+            std::memcpy(sub_off, h->lp.loc_off.data(), (h->lp.S + 1) * 8);
+        }
+    });
+}
+
+int ldopf_get_history(const ldopf_problem* h, double* hist, int64_t cap_rows, int64_t* len) {
+    return guard([&] {
+        need(h, "handle");
+        need(len, "len");
+        *len = h->hist_len;
+        if (!hist) return;
+        if (cap_rows < h->hist_len) fail(LDOPF_BUFFER_TOO_SMALL, "history needs len rows");
+        if (h->hist_len > 0) {
+            hip_check(hipMemcpyAsync(hist, h->hist.p, h->hist_len * 4 * 8, hipMemcpyDeviceToHost, h->stream), "download history");
+            hip_check(hipStreamSynchronize(h->stream), "download history");
+        }
+    });
+}
+
+int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t cap_abar, double* bbar, int64_t cap_bbar,
+                        int32_t* rank, int64_t cap_rank) {
+    return guard([&] {
+        need(h, "handle");
+        const int64_t words = int64_t(h->abar.count);
+        const int64_t nl = int64_t(h->lp.gidx.size());
+        if (abar) {
+            if (cap_abar < words) fail(LDOPF_BUFFER_TOO_SMALL, "abar needs op_words entries");
+            hip_check(hipMemcpyAsync(abar, h->abar.p, words * 8, hipMemcpyDeviceToHost, h->stream), "download abar");
+        }
+        if (bbar) {
+            if (cap_bbar < nl) fail(LDOPF_BUFFER_TOO_SMALL, "bbar needs N_loc entries");
+            hip_check(hipMemcpyAsync(bbar, h->bbar.p, nl * 8, hipMemcpyDeviceToHost, h->stream), "download bbar");
+        }
+        if (rank) {
+            if (cap_rank < h->lp.S) fail(LDOPF_BUFFER_TOO_SMALL, "rank needs S entries");
+            std::memcpy(rank, h->rank.data(), h->lp.S * 4);
+        }
+        hip_check(hipStreamSynchronize(h->stream), "download operators");
+    });
+}
+
+int ldopf_objective(const ldopf_problem* h, double* f) {
+    return guard([&] {
+        need(h, "handle");
+        need(f, "f");
+        std::vector<double> x(h->lp.n);
+        hip_check(hipMemcpyAsync(x.data(), h->x.p, h->lp.n * 8, hipMemcpyDeviceToHost, h->stream), "download x");
+        hip_check(hipStreamSynchronize(h->stream), "download x");
+        double acc = 0.0;
+        for (int64_t g = 0; g < h->lp.n; ++g) acc += h->lp.c[g] * x[g];
+        *f = acc;
+    });
+}
+
+int ldopf_get_global_device(const ldopf_problem* h, double* x_device, int64_t cap) {
+    return guard([&] {
+        need(h, "handle");
+        need(x_device, "x_device");
+        if (cap < h->lp.n) fail(LDOPF_BUFFER_TOO_SMALL, "x needs n entries");
+        hip_check(hipMemcpyAsync(x_device, h->x.p, h->lp.n * 8, hipMemcpyDeviceToDevice, h->stream), "copy x");
+    });
+}
+
+int ldopf_get_local_device(const ldopf_problem* h, double* xs_device, double* lam_device, int64_t cap) {
+    return guard([&] {
+        need(h, "handle");
+        const int64_t nl = int64_t(h->lp.gidx.size());
+        if (cap < nl) fail(LDOPF_BUFFER_TOO_SMALL, "x_s and lambda need N_loc entries");
+        if (xs_device) hip_check(hipMemcpyAsync(xs_device, h->xs.p, nl * 8, hipMemcpyDeviceToDevice, h->stream), "copy x_s");
+        if (lam_device) hip_check(hipMemcpyAsync(lam_device, h->lam.p, nl * 8, hipMemcpyDeviceToDevice, h->stream), "copy lambda");
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Argument blocks and launchers of the device kernels (see device.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace ldopf {
+
+struct PrecomputeArgs {
+    int64_t S;
+    const int32_t* ns;
+    const int32_t* ms;
+    const int64_t* a_off;      // words of A before subsystem s
+    const int64_t* row_off;    // rows (entries of b) before s
+    const int64_t* loc_off;    // copies before s
+    const int64_t* basis_off;  // n_s * n_s words before s
+    const double* A;
+    const double* b;
+    double* basis;  // out: n_s x n_s orthonormal rows, row space first
+    double* abar;   // out: dense Abar_s, row-major
+    double* bbar;   // out: per copy
+    int32_t* rank;  // out
+    int32_t* flags; // out: 1 = inconsistent dependent row
+    double tol_dep; // a row is dependent when its residual norm is below tol_dep * its norm
+    double tol_rhs; // ... and then its right-hand side must be below tol_rhs * (1 + max |b_s|)
+};
+
+struct SweepStatus {
+    int64_t iters;
+    int32_t converged;
+    int32_t flags;  // 1: barrier wait timed out, 2: non-finite residuals
+    double pres, dres, eps_p, eps_d;
+};
+
+template <typename T>
+struct SweepArgs {
+    const PartInfo* parts;
+    const SubMeta* subs;
+    const int32_t* row_canon;
+    const uint16_t* row_lvar;
+    const uint16_t* row_sub;
+    const int32_t* var_gid;
+    const int32_t* var_slot;
+    const int32_t* var_slot_lo;
+    const int32_t* var_slot_hi;
+    const uint8_t* var_writer;
+    const uint16_t* var_copy_off;
+    const uint16_t* var_copy_rows;
+    const uint16_t* tk_sub;
+    const double* basis;
+    const double* bbar;  // per copy, canonical order
+    const double* c;
+    const double* lo;
+    const double* hi;
+    const double* cnt;   // copies per global variable
+    double* xs;          // state in and out, canonical copy order
+    double* lam;
+    double* x;           // global x out
+    T* bpart;            // [2][n_slots] boundary partial sums
+    double* rpart;       // [2][P][8] residual partial sums
+    unsigned* bar;       // [0] arrivals, [64] generation
+    double* hist;        // [hist_cap][4]
+    int64_t hist_cap;
+    SweepStatus* st;
+    double rho, eps_rel, eps_abs;
+    int64_t max_iter;
+    int64_t nloc;
+    int64_t n_slots;
+    int32_t check;
+    int32_t P;
+    uint64_t spin_limit; // wall-clock ticks a barrier may wait
+};
+
+hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream);
+hipError_t prepare_sweep(bool fp32, size_t lds_bytes);
+hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_sweep(const SweepArgs<double>& a, int grid, int block, size_t lds, hipStream_t stream);
+hipError_t launch_sweep(const SweepArgs<float>& a, int grid, int block, size_t lds, hipStream_t stream);
+
+}  // namespace ldopf

@@ -1,0 +1,554 @@
+// Device side of libldopf for gfx950 (CDNA4, wave64).
+//
+//  * precompute_kernel: once per network, FP64. For every subsystem, one wave
+//    builds an orthonormal basis of R^{n_s} whose first rank_s rows span the
+//    row space of A_s (modified Gram-Schmidt, two passes), completes it with
+//    the orthogonal complement, and from it the operators of closed_2:
+//    Abar_s = Q'Q - I (Q the row-space rows) and bbar_s = Q' beta, the
+//    minimum-norm solution of A_s x = b_s. At full row rank these equal
+//    A_s'(A_s A_s')^-1 A_s - I and A_s'(A_s A_s')^-1 b_s (Section III-B); a
+//    dependent row is dropped after checking that its right-hand side is
+//    consistent (the "row reduction" the paper asks for).
+//
+//  * sweep_kernel<T>: the ADMM loop of Algorithm 1 in one persistent,
+//    cooperative launch. Each workgroup owns a run of subsystems and keeps
+//    their operators (rank form), bbar, x_s and lambda in LDS for the whole
+//    solve. One iteration: global update closed_1 for the variables the
+//    workgroup touches, local update closed_2 in rank form, dual update
+//    ADMM-3, residual partial sums in FP64, publication of the boundary
+//    partial sums, one grid barrier, and the termination test of Section
+//    III-C evaluated identically by every workgroup.
+//
+// The local update in rank form: with W the K_s rows of the smaller of the
+// row-space basis (mode 1) and the complement basis (mode 0),
+//   -Abar_s v = v - W'(W v)   (mode 1)   or   W'(W v)   (mode 0),
+// so x_s = bbar_s - Abar_s (z + lambda / rho), the projection of
+// z + lambda / rho onto {A_s x = b_s}, costs 2 K_s n_s instead of n_s^2.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "internal.h"
+#include "layout.h"
+#include "device.h"
+
+namespace ldopf {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+    // xor butterfly: every lane ends with the same bits (addition commutes)
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ inline void st_agent(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(float* p, float v) {
+    __hip_atomic_store(reinterpret_cast<unsigned int*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_agent(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ inline float ld_agent(const float* p) {
+    return __uint_as_float(__hip_atomic_load(reinterpret_cast<unsigned int*>(const_cast<float*>(p)), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Operator precompute (FP64). One wave per subsystem, lane l owns columns
+// l, l + 64, l + 128, l + 192 (n_s <= 255); the work row lives in registers,
+// basis rows in global memory (each lane only touches its own columns).
+
+__global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs a) {
+    __shared__ double sbeta[4][256];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t s = int64_t(blockIdx.x) * 4 + wv;
+    if (s >= a.S) return;
+    const int n = a.ns[s], m = a.ms[s];
+    const double* As = a.A + a.a_off[s];
+    const double* bs = a.b + a.row_off[s];
+    double* U = a.basis + a.basis_off[s];
+    double* beta = sbeta[wv];
+    double bmax = 0.0;
+    for (int i = 0; i < m; ++i) bmax = fmax(bmax, fabs(bs[i]));
+    int r = 0, bad = 0;
+    for (int i = 0; i < m; ++i) {
+        double ar[4];
+        double nn = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = lane + 64 * q;
+            ar[q] = c < n ? As[int64_t(i) * n + c] : 0.0;
+            nn += ar[q] * ar[q];
+        }
+        const double nrm0 = sqrt(wave_sum(nn));
+        double bi = bs[i];
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int k = 0; k < r; ++k) {
+                double d = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = lane + 64 * q;
+                    if (c < n) d += ar[q] * U[int64_t(k) * n + c];
+                }
+                d = wave_sum(d);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = lane + 64 * q;
+                    if (c < n) ar[q] -= d * U[int64_t(k) * n + c];
+                }
+                bi -= d * beta[k];
+            }
+        }
+        nn = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nn += ar[q] * ar[q];
+        const double nr = sqrt(wave_sum(nn));
+        if (nrm0 > 0.0 && nr > a.tol_dep * nrm0 && r < n) {
+            const double inv = 1.0 / nr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = lane + 64 * q;
+                if (c < n) U[int64_t(r) * n + c] = ar[q] * inv;
+            }
+            if (lane == 0) beta[r] = bi * inv;
+            ++r;
+        } else if (fabs(bi) > a.tol_rhs * (1.0 + bmax)) {
+            bad = 1;  // dependent row with an inconsistent right-hand side
+        }
+    }
+    // complete the basis: greedily take the unit vector farthest from the span
+    for (int q2 = r; q2 < n; ++q2) {
+        double best = -1.0;
+        int bidx = 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = lane + 64 * q;
+            if (c < n) {
+                double res = 1.0;
+                for (int k = 0; k < q2; ++k) {
+                    const double u = U[int64_t(k) * n + c];
+                    res -= u * u;
+                }
+                if (res > best) { best = res; bidx = c; }
+            }
+        }
+        for (int mm = 32; mm >= 1; mm >>= 1) {
+            const double ob = __shfl_xor(best, mm, 64);
+            const int oi = __shfl_xor(bidx, mm, 64);
+            if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+        }
+        double ar[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ar[q] = (lane + 64 * q) == bidx ? 1.0 : 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int k = 0; k < q2; ++k) {
+                double d = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = lane + 64 * q;
+                    if (c < n) d += ar[q] * U[int64_t(k) * n + c];
+                }
+                d = wave_sum(d);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = lane + 64 * q;
+                    if (c < n) ar[q] -= d * U[int64_t(k) * n + c];
+                }
+            }
+        }
+        double nn = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nn += ar[q] * ar[q];
+        const double inv = 1.0 / sqrt(wave_sum(nn));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = lane + 64 * q;
+            if (c < n) U[int64_t(q2) * n + c] = ar[q] * inv;
+        }
+    }
+    // bbar = Q' beta over the row-space rows
+    double* bb = a.bbar + a.loc_off[s];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = lane + 64 * q;
+        if (c < n) {
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc += beta[k] * U[int64_t(k) * n + c];
+            bb[c] = acc;
+        }
+    }
+    // dense Abar = Q'Q - I; entry (i, c) needs column i, owned by lane i % 64
+    double* Ab = a.abar + a.basis_off[s];
+    for (int i = 0; i < n; ++i) {
+        const int owner = i & 63;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < r; ++k) {
+            const double mine = lane == owner ? U[int64_t(k) * n + i] : 0.0;
+            const double ui = __shfl(mine, owner, 64);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = lane + 64 * q;
+                if (c < n) acc[q] += ui * U[int64_t(k) * n + c];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = lane + 64 * q;
+            if (c < n) Ab[int64_t(i) * n + c] = acc[q] - (c == i ? 1.0 : 0.0);
+        }
+    }
+    if (lane == 0) {
+        a.rank[s] = r;
+        a.flags[s] = bad;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent sweep.
+
+namespace {
+
+struct SubLds {
+    uint16_t row0;
+    uint8_t n, k;
+    uint16_t t0, mode;
+    uint32_t w0;
+    uint32_t pad;
+};
+static_assert(sizeof(SubLds) == 16, "SubLds layout");
+
+// Grid-wide barrier over the co-resident workgroups of a cooperative launch.
+// Thread 0 arrives with an acquire-release add on the arrival counter; the
+// last arriver resets it and publishes the new generation with a release
+// store. Waiting is bounded by a wall-clock limit so that a broken launch
+// ends instead of hanging; the caller sees the failure in the return value.
+__device__ inline bool grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks, unsigned& epoch,
+                                    uint64_t limit, int* ok_lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ++epoch;
+        int ok = 1;
+        if (nblocks > 1) {
+            const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == nblocks - 1) {
+                __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (wall_clock64() - t0 > limit) {
+                        ok = 0;
+                        break;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+        }
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int bar_ok;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    const PartInfo pi = a.parts[blockIdx.x];
+    const LdsLayout L = lds_layout(sizeof(T), uint32_t(pi.w_words), uint32_t(pi.n_row), uint32_t(pi.n_tk),
+                                   uint32_t(pi.n_var), uint32_t(pi.n_sub), uint32_t(nw));
+    T* W = reinterpret_cast<T*>(smem + L.W);
+    T* bbar = reinterpret_cast<T*>(smem + L.bbar);
+    T* xs[2] = {reinterpret_cast<T*>(smem + L.xs0), reinterpret_cast<T*>(smem + L.xs1)};
+    T* lam[2] = {reinterpret_cast<T*>(smem + L.lam0), reinterpret_cast<T*>(smem + L.lam1)};
+    T* vb = reinterpret_cast<T*>(smem + L.v);
+    T* tb = reinterpret_cast<T*>(smem + L.t);
+    T* xloc = reinterpret_cast<T*>(smem + L.xloc);
+    T* ownp = reinterpret_cast<T*>(smem + L.ownp);
+    T* crho = reinterpret_cast<T*>(smem + L.crho);
+    T* vlo = reinterpret_cast<T*>(smem + L.lo);
+    T* vhi = reinterpret_cast<T*>(smem + L.hi);
+    T* vcnt = reinterpret_cast<T*>(smem + L.cnt);
+    int32_t* slo = reinterpret_cast<int32_t*>(smem + L.slot_lo);
+    int32_t* shi = reinterpret_cast<int32_t*>(smem + L.slot_hi);
+    int32_t* sown = reinterpret_cast<int32_t*>(smem + L.slot_own);
+    uint16_t* rlv = reinterpret_cast<uint16_t*>(smem + L.row_lvar);
+    uint16_t* rsub = reinterpret_cast<uint16_t*>(smem + L.row_sub);
+    uint16_t* coff = reinterpret_cast<uint16_t*>(smem + L.copy_off);
+    uint16_t* crow = reinterpret_cast<uint16_t*>(smem + L.copy_rows);
+    uint16_t* tks = reinterpret_cast<uint16_t*>(smem + L.tk_sub);
+    SubLds* meta = reinterpret_cast<SubLds*>(smem + L.meta);
+    double* red = reinterpret_cast<double*>(smem + L.red);
+    double* tot = red + 8 * nw;
+
+    const T rho = T(a.rho);
+    const T irho = T(1.0 / a.rho);
+    const int R = pi.n_row, V = pi.n_var, TK = pi.n_tk;
+
+    // ---- load this part into LDS
+    for (int i = tid; i < pi.n_sub; i += nt) {
+        const SubMeta m = a.subs[pi.sub_begin + i];
+        meta[i] = SubLds{m.row0, m.n, m.k, m.t0, m.mode, m.w0, 0u};
+    }
+    for (int r = tid; r < R; r += nt) {
+        const int canon = a.row_canon[pi.row_begin + r];
+        bbar[r] = T(a.bbar[canon]);
+        xs[0][r] = T(a.xs[canon]);
+        lam[0][r] = T(a.lam[canon]);
+        rlv[r] = a.row_lvar[pi.row_begin + r];
+        rsub[r] = a.row_sub[pi.row_begin + r];
+        crow[r] = a.var_copy_rows[pi.copy_begin + r];
+    }
+    for (int v = tid; v <= V; v += nt) coff[v] = a.var_copy_off[pi.coff_begin + v];
+    for (int v = tid; v < V; v += nt) {
+        const int g = a.var_gid[pi.var_begin + v];
+        crho[v] = T(a.c[g] / a.rho);
+        vlo[v] = T(a.lo[g]);
+        vhi[v] = T(a.hi[g]);
+        vcnt[v] = T(a.cnt[g]);
+        slo[v] = a.var_slot_lo[pi.var_begin + v];
+        shi[v] = a.var_slot_hi[pi.var_begin + v];
+        sown[v] = a.var_slot[pi.var_begin + v];
+    }
+    for (int q = tid; q < TK; q += nt) tks[q] = a.tk_sub[pi.tk_begin + q];
+    for (int i = wv; i < pi.n_sub; i += nw) {
+        const SubMeta m = a.subs[pi.sub_begin + i];
+        const int kn = int(m.k) * int(m.n);
+        for (int q = lane; q < kn; q += 64) {
+            const int k = q / m.n, j = q - k * m.n;
+            W[m.w0 + q] = T(a.basis[m.basis + uint64_t(m.brow + k) * m.n + j]);
+        }
+    }
+    __syncthreads();
+
+    // ---- partial sums of the starting state for the first global update
+    const int64_t ns = a.n_slots;
+    for (int v = tid; v < V; v += nt) {
+        T acc = T(0);
+        for (int q = coff[v]; q < coff[v + 1]; ++q) {
+            const int r = crow[q];
+            acc += xs[0][r] - lam[0][r] * irho;
+        }
+        ownp[v] = acc;
+        if (sown[v] >= 0) st_agent(a.bpart + sown[v], acc);
+    }
+    // every wave's published stores complete before its workgroup arrives
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    unsigned epoch = 0;
+    const unsigned P = unsigned(a.P);
+    bool ok = grid_barrier(a.bar, a.bar + 64, P, epoch, a.spin_limit, &bar_ok);
+
+    int64_t done = 0;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0, d4 = 0.0;
+    int converged = 0, nonfinite = 0;
+    while (ok && done < a.max_iter) {
+        const int cur = int(done & 1), nx = cur ^ 1;
+        const T* bcur = a.bpart + int64_t(cur) * ns;
+        T* bnx = a.bpart + int64_t(nx) * ns;
+        // closed_1: clipped average of the copies
+        for (int v = tid; v < V; v += nt) {
+            T s;
+            if (slo[v] < 0) {
+                s = ownp[v];
+            } else {
+                s = T(0);
+                for (int q = slo[v]; q < shi[v]; ++q) s += ld_agent(bcur + q);
+            }
+            T xv = (s - crho[v]) / vcnt[v];
+            xv = xv < vlo[v] ? vlo[v] : xv;
+            xv = xv > vhi[v] ? vhi[v] : xv;
+            xloc[v] = xv;
+        }
+        __syncthreads();
+        // v = B_s x + lambda_s / rho
+        const T* lc = lam[cur];
+        for (int r = tid; r < R; r += nt) vb[r] = xloc[rlv[r]] + lc[r] * irho;
+        __syncthreads();
+        // t = W v, one task per (subsystem, basis row)
+        for (int q = tid; q < TK; q += nt) {
+            const SubLds m = meta[tks[q]];
+            const int k = q - m.t0;
+            const T* wr = W + m.w0 + k * m.n;
+            const T* vv = vb + m.row0;
+            T acc = T(0);
+            for (int j = 0; j < m.n; ++j) acc += wr[j] * vv[j];
+            tb[q] = acc;
+        }
+        __syncthreads();
+        // closed_2 in rank form, then ADMM-3; residual sums in FP64
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
+        const T* xc = xs[cur];
+        T* xn = xs[nx];
+        T* ln = lam[nx];
+        for (int r = tid; r < R; r += nt) {
+            const SubLds m = meta[rsub[r]];
+            const int j = r - m.row0;
+            T acc = T(0);
+            for (int k = 0; k < m.k; ++k) acc += W[m.w0 + k * m.n + j] * tb[m.t0 + k];
+            const T vr = vb[r];
+            const T y = m.mode ? bbar[r] + (vr - acc) : bbar[r] + acc;
+            const T z = xloc[rlv[r]];
+            const T lnew = lc[r] + rho * (z - y);
+            xn[r] = y;
+            ln[r] = lnew;
+            const double dz = double(z) - double(y);
+            const double dx = double(y) - double(xc[r]);
+            p0 += dz * dz;
+            p1 += dx * dx;
+            p2 += double(z) * double(z);
+            p3 += double(y) * double(y);
+            p4 += double(lnew) * double(lnew);
+        }
+        p0 = wave_sum(p0);
+        p1 = wave_sum(p1);
+        p2 = wave_sum(p2);
+        p3 = wave_sum(p3);
+        p4 = wave_sum(p4);
+        if (lane == 0) {
+            red[wv * 8 + 0] = p0;
+            red[wv * 8 + 1] = p1;
+            red[wv * 8 + 2] = p2;
+            red[wv * 8 + 3] = p3;
+            red[wv * 8 + 4] = p4;
+        }
+        __syncthreads();
+        // partial sums for the next global update; publish boundary slots
+        for (int v = tid; v < V; v += nt) {
+            T acc = T(0);
+            for (int q = coff[v]; q < coff[v + 1]; ++q) {
+                const int r = crow[q];
+                acc += xn[r] - ln[r] * irho;
+            }
+            ownp[v] = acc;
+            if (sown[v] >= 0) st_agent(bnx + sown[v], acc);
+        }
+        if (tid < 5) {
+            double acc = 0.0;
+            for (int w = 0; w < nw; ++w) acc += red[w * 8 + tid];
+            st_agent(a.rpart + (int64_t(nx) * P + blockIdx.x) * 8 + tid, acc);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        ok = grid_barrier(a.bar, a.bar + 64, P, epoch, a.spin_limit, &bar_ok);
+        if (!ok) break;
+        // termination test (Section III-C) from the grid-wide sums, computed
+        // the same way by every workgroup
+        if (wv == 0) {
+            for (int q = 0; q < 5; ++q) {
+                double acc = 0.0;
+                for (unsigned p = lane; p < P; p += 64) acc += ld_agent(a.rpart + (int64_t(nx) * P + p) * 8 + q);
+                acc = wave_sum(acc);
+                if (lane == 0) tot[q] = acc;
+            }
+        }
+        __syncthreads();
+        d0 = tot[0];
+        d1 = tot[1];
+        d2 = tot[2];
+        d3 = tot[3];
+        d4 = tot[4];
+        ++done;
+        const double pres = sqrt(d0), dres = a.rho * sqrt(d1);
+        const double sq = sqrt(double(a.nloc));
+        const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d2), sqrt(d3));
+        const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d4);
+        if (blockIdx.x == 0 && tid == 0 && done <= a.hist_cap) {
+            double* h = a.hist + (done - 1) * 4;
+            h[0] = pres;
+            h[1] = dres;
+            h[2] = eps_p;
+            h[3] = eps_d;
+        }
+        nonfinite = !isfinite(d0 + d1 + d2 + d3 + d4);
+        converged = pres <= eps_p && dres <= eps_d;
+        if (nonfinite || (a.check && converged)) break;
+    }
+    // ---- write the state back (canonical order, FP64)
+    const int fp = int(done & 1);
+    for (int r = tid; r < R; r += nt) {
+        const int canon = a.row_canon[pi.row_begin + r];
+        a.xs[canon] = double(xs[fp][r]);
+        a.lam[canon] = double(lam[fp][r]);
+    }
+    if (done > 0)
+        for (int v = tid; v < V; v += nt)
+            if (a.var_writer[pi.var_begin + v]) a.x[a.var_gid[pi.var_begin + v]] = double(xloc[v]);
+    if (tid == 0 && (!ok || nonfinite)) atomicOr(&a.st->flags, (ok ? 0 : 1) | (nonfinite ? 2 : 0));
+    if (blockIdx.x == 0 && tid == 0) {
+        a.st->iters = done;
+        a.st->converged = converged;
+        a.st->pres = sqrt(d0);
+        a.st->dres = a.rho * sqrt(d1);
+        const double sq = sqrt(double(a.nloc));
+        a.st->eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d2), sqrt(d3));
+        a.st->eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d4);
+    }
+}
+
+__global__ void reset_sync_kernel(unsigned* bar, SweepStatus* st) {
+    // plain stores; run on the same stream before every sweep launch
+    const int t = threadIdx.x;
+    if (t < 128) bar[t] = 0u;
+    if (t == 0) {
+        st->iters = 0;
+        st->converged = 0;
+        st->flags = 0;
+        st->pres = st->dres = st->eps_p = st->eps_d = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream) {
+    const unsigned grid = unsigned((a.S + 3) / 4);
+    hipLaunchKernelGGL(precompute_kernel, dim3(grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static const void* sweep_ptr() {
+    return reinterpret_cast<const void*>(&sweep_kernel<T>);
+}
+
+hipError_t prepare_sweep(bool fp32, size_t lds_bytes) {
+    const void* f = fp32 ? sweep_ptr<float>() : sweep_ptr<double>();
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+}
+
+hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu) {
+    const void* f = fp32 ? sweep_ptr<float>() : sweep_ptr<double>();
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
+}
+
+template <typename T>
+static hipError_t launch_sweep_t(SweepArgs<T> a, int grid, int block, size_t lds, unsigned* bar, SweepStatus* st,
+                                 hipStream_t stream) {
+    hipLaunchKernelGGL(reset_sync_kernel, dim3(1), dim3(128), 0, stream, bar, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* args[] = {&a};
+    return hipLaunchCooperativeKernel(sweep_ptr<T>(), dim3(grid), dim3(block), args, unsigned(lds), stream);
+}
+
+hipError_t launch_sweep(const SweepArgs<double>& a, int grid, int block, size_t lds, hipStream_t stream) {
+    return launch_sweep_t<double>(a, grid, block, lds, a.bar, a.st, stream);
+}
+hipError_t launch_sweep(const SweepArgs<float>& a, int grid, int block, size_t lds, hipStream_t stream) {
+    return launch_sweep_t<float>(a, grid, block, lds, a.bar, a.st, stream);
+}
+
+}  // namespace ldopf

@@ -1,0 +1,64 @@
+// LDS layout of one workgroup of the persistent sweep kernel. Used by the host
+// planner (to size and balance parts) and by the kernel (to carve its dynamic
+// shared memory), so both agree byte for byte.
+#pragma once
+
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#define LDOPF_HD __host__ __device__
+#else
+#define LDOPF_HD
+#endif
+
+namespace ldopf {
+
+struct LdsLayout {
+    uint32_t W, bbar, xs0, xs1, lam0, lam1, v, t, xloc, ownp, crho, lo, hi, cnt;  // T arrays
+    uint32_t slot_lo, slot_hi, slot_own;                                         // int32 per var
+    uint32_t row_lvar, row_sub, copy_off, copy_rows, tk_sub, meta;                // index arrays
+    uint32_t red;                                                                // double [waves][8]
+    uint32_t total;
+};
+
+LDOPF_HD inline uint32_t lds_align(uint32_t x) { return (x + 15u) & ~15u; }
+
+// w: bytes of the bulk type (8 FP64, 4 FP32); counts of one part.
+LDOPF_HD inline LdsLayout lds_layout(uint32_t w, uint32_t w_words, uint32_t rows, uint32_t tks,
+                                     uint32_t vars, uint32_t subs, uint32_t waves) {
+    LdsLayout L{};
+    uint32_t o = 0;
+    auto take = [&](uint32_t bytes) {
+        uint32_t at = o;
+        o = lds_align(o + bytes);
+        return at;
+    };
+    L.W = take(w * w_words);
+    L.bbar = take(w * rows);
+    L.xs0 = take(w * rows);
+    L.xs1 = take(w * rows);
+    L.lam0 = take(w * rows);
+    L.lam1 = take(w * rows);
+    L.v = take(w * rows);
+    L.t = take(w * tks);
+    L.xloc = take(w * vars);
+    L.ownp = take(w * vars);
+    L.crho = take(w * vars);
+    L.lo = take(w * vars);
+    L.hi = take(w * vars);
+    L.cnt = take(w * vars);
+    L.slot_lo = take(4 * vars);
+    L.slot_hi = take(4 * vars);
+    L.slot_own = take(4 * vars);
+    L.row_lvar = take(2 * rows);
+    L.row_sub = take(2 * rows);
+    L.copy_off = take(2 * (vars + 1));
+    L.copy_rows = take(2 * rows);
+    L.tk_sub = take(2 * tks);
+    L.meta = take(16 * subs);
+    L.red = take(8 * 8 * (waves + 1));  // per-wave partial sums, then the grid totals
+    L.total = o;
+    return L;
+}
+
+}  // namespace ldopf
