@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""ADMM iter/s and time to the 1e-4 residual on the 8500-bus synthetic feeder.
+
+One step = one full solve of the closed-form ADMM (Algorithm 1: global
+update, local update, dual update, termination test at eps_rel = 1e-4, rho =
+100) from the initial point, on the seed-8500 synthetic radial three-phase
+feeder with about 8500 buses, 70% single-phase laterals and lognormal loads.
+The network is assembled, decomposed, uploaded and its operators precomputed
+on the GPU before timing (the precompute time is reported beside the result);
+the timed region is the solve itself with every input resident in HBM.
+
+Prints one JSON line. ``--gpus N`` with N > 1 is refused: the solver runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PROFILE_MD = os.path.join(ROOT, "profiles", "sweep_fp64_8500bus_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2310_09410_amd", "csrc", "device.hip")
+WORKLOAD = ("8500-bus synthetic radial 3-phase feeder (seed 8500; 20/10/70% three/two/single-phase lines; "
+            "lognormal(ln 5 kW, 0.8) per-phase loads, Q = 0.3 P; one substation generator), "
+            "plain FP64 ADMM to eps_rel = 1e-4, rho = 100")
+
+
+def algorithmic_bytes_per_sweep(sizes, w: int) -> float:
+    """Compulsory bytes of one sweep: the rank-form operators and bbar, the
+    local copies' x_s and lambda read and written plus their int32 global
+    index, and the global x written and gathered with its lo, hi and c."""
+    return (w * (sizes.rank_words + sizes.n_local) + sizes.n_local * (4 * w + 4) + sizes.n * 5 * w)
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per sweep-kernel launch from the committed counter summary,
+    or None when it is missing or was taken on a different kernel source."""
+    if not os.path.exists(PROFILE_MD):
+        return None
+    text = open(PROFILE_MD).read()
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_t or m_sha.group(1) != kernel_sha():
+        return None
+    return float(m_t.group(1))
+
+
+def cpu_baseline(sweeps: int) -> dict:
+    """The FP64 oracle timed on this host: a bounded sample of sweeps of the
+    same feeder after its precompute. Runs in a child process pinned to one
+    BLAS/OpenMP thread so the core count is exact."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", str(sweeps)],
+                         env=env, capture_output=True, text=True, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def _cpu_baseline_child(sweeps: int):
+    from oracle import admm, model
+    from synth import make_feeder
+    net = make_feeder("8500", 8500)
+    prep = admm.prepare(model.decompose(net))
+    t0 = time.perf_counter()
+    admm.solve(prep, max_iter=sweeps, check=False)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"value": sweeps / dt, "unit": "iter/s", "cores": 1, "kind": "oracle",
+                      "sample": f"{sweeps} FP64 oracle sweeps (global, local, dual update and residuals) of the "
+                                f"same 8500-bus feeder after its precompute, {dt:.1f} s, one thread"}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-sweeps", type=int, default=3000, help="oracle sweeps timed for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="one copy of known size and one solve, for rocprofv3 counter runs")
+    ap.add_argument("--cpu-baseline-only", type=int, default=0, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.cpu_baseline_only:
+        _cpu_baseline_child(args.cpu_baseline_only)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent solves shard across GPUs without communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2310_09410_amd as P
+    from paper_2310_09410_amd import ldopf as L
+    from synth import make_feeder
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    net = make_feeder("8500", 8500)
+
+    if args.profile_pass:
+        n = 256 << 20  # 1 GiB of float32 read and 1 GiB written: past the 256 MB cache
+        x = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+        y = torch.empty_like(x)
+        y.copy_(x)
+        prob = P.ldopf_create(net, P.ldopf_default_options(), stream=stream)
+        st = prob.solve()
+        torch.cuda.synchronize()
+        prob.close()
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "sweeps_computed": st.sweeps_computed,
+                          "sweep_ms": st.sweep_ms, "kernel_source_sha256": kernel_sha()}))
+        return
+
+    def run(precision):
+        prob = P.ldopf_create(net, P.ldopf_default_options(precision=precision), stream=stream)
+        for _ in range(args.warmup):
+            prob.reset()
+            prob.solve()
+        torch.cuda.synchronize()
+        iters = computed = 0
+        kms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            prob.reset()
+            st = prob.solve()
+            iters += st.iterations
+            computed += st.sweeps_computed
+            kms.append(st.sweep_ms)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return prob, st, iters, computed, kms, dt
+
+    prob, st, iters, computed, kms, dt = run(L.LDOPF_FP64)
+    sizes = prob.sizes()
+    obj = prob.objective()
+    b_sweep = algorithmic_bytes_per_sweep(sizes, 8)
+    launch_ms = sum(kms) / len(kms)
+    sweeps_per_launch = computed / args.steps
+    achieved = b_sweep * sweeps_per_launch / (launch_ms * 1e-3) / 1e9
+    rec = {
+        "metric": "ADMM iter/s (8500-bus feeder, to eps_rel 1e-4)",
+        "value": iters / dt,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "buses": net["n_bus"], "subsystems": sizes.n_sub,
+                   "global_vars": sizes.n, "local_copies": sizes.n_local, "workgroups": sizes.n_parts,
+                   "block_threads": sizes.block_threads, "lds_bytes_per_workgroup": sizes.lds_bytes},
+        "iterations_to_tol": st.iterations,
+        "time_to_tol_s": 1e-3 * launch_ms,
+        "us_per_sweep": 1e3 * launch_ms / sweeps_per_launch,
+        "precompute_ms": st.precompute_ms,
+        "objective": obj,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
+                     "kernel": "sweep_kernel<double> (one persistent launch per solve)",
+                     "bytes_per_sweep": b_sweep, "sweeps_per_launch": sweeps_per_launch,
+                     "launch_ms": launch_ms},
+    }
+    prob.close()
+    if not args.no_fp32:
+        p32, st32, it32, c32, k32, dt32 = run(L.LDOPF_FP32_MIXED)
+        s32 = p32.sizes()
+        rec["fp32_mixed"] = {"iter_per_s": it32 / dt32, "iterations_to_tol": st32.iterations,
+                             "time_to_tol_s": 1e-3 * sum(k32) / len(k32),
+                             "us_per_sweep": 1e3 * sum(k32) / c32,
+                             "achieved_GBs": algorithmic_bytes_per_sweep(s32, 4) * c32 / (1e-3 * sum(k32)) / 1e9,
+                             "objective": p32.objective(), "objective_rel_diff_vs_fp64":
+                                 abs(p32.objective() - obj) / max(1.0, abs(obj))}
+        p32.close()
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(args.cpu_sweeps)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

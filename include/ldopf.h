@@ -150,7 +150,8 @@ typedef struct ldopf_options {
     int32_t history;         /* 1 (default): record pres, dres, eps_prim, eps_dual per sweep */
     int32_t rows_per_part;   /* tuning: local copies per workgroup; 0 = automatic */
     int32_t block_threads;   /* tuning: threads per workgroup (64..1024, multiple of 64); 0 = automatic */
-    int32_t reserved[6];     /* must be zero */
+    int32_t profile;         /* 1: record per-phase device time of the sweep (ldopf_get_phase_times); default 0 */
+    int32_t reserved[5];     /* must be zero */
 } ldopf_options;
 
 typedef struct ldopf_sizes {
@@ -173,6 +174,9 @@ typedef struct ldopf_status {
     double pres, dres, eps_prim, eps_dual; /* last sweep */
     double sweep_ms;      /* device time of the sweep kernel (HIP events on the handle's stream) */
     double precompute_ms; /* device time of the operator precompute at creation */
+    int64_t sweeps_computed; /* sweeps the kernel ran: the test of a sweep is evaluated while the
+                                next one runs, so a converged solve computes one sweep more than
+                                it returns */
 } ldopf_status;
 
 typedef struct ldopf_problem ldopf_problem;
@@ -255,6 +259,13 @@ LDOPF_API int ldopf_get_history(const ldopf_problem* h, double* hist, int64_t ca
  * bbar [N_loc], numerical rank of each A_s [S]; any pointer may be NULL. */
 LDOPF_API int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t cap_abar,
                                   double* bbar, int64_t cap_bbar, int32_t* rank, int64_t cap_rank);
+/* Per-phase device time of the last solve with options.profile = 1, in ms,
+ * measured by workgroup 0 with the wall clock: [0] global update, [1]
+ * gather of B_s x + lambda/rho, [2] t = W v, [3] local and dual update with
+ * residual sums, [4] partial sums and publication, [5] grid barrier,
+ * [6] termination test, [7] unused. Zeros when profiling was off. */
+LDOPF_API int ldopf_get_phase_times(const ldopf_problem* h, double ms[8]);
+
 /* c'x at the last sweep's global x. */
 LDOPF_API int ldopf_objective(const ldopf_problem* h, double* f);
 

@@ -54,7 +54,7 @@ class ldopf_options(C.Structure):
         ("rho", C.c_double), ("eps_rel", C.c_double), ("eps_abs", C.c_double), ("max_iter", C.c_int64),
         ("precision", C.c_int32), ("residual_form", C.c_int32), ("check_termination", C.c_int32),
         ("history", C.c_int32), ("rows_per_part", C.c_int32), ("block_threads", C.c_int32),
-        ("reserved", C.c_int32 * 6),
+        ("profile", C.c_int32), ("reserved", C.c_int32 * 5),
     ]
 
 
@@ -70,7 +70,7 @@ class ldopf_status(C.Structure):
     _fields_ = [
         ("iterations", C.c_int64), ("converged", C.c_int32), ("code", C.c_int32),
         ("pres", C.c_double), ("dres", C.c_double), ("eps_prim", C.c_double), ("eps_dual", C.c_double),
-        ("sweep_ms", C.c_double), ("precompute_ms", C.c_double),
+        ("sweep_ms", C.c_double), ("precompute_ms", C.c_double), ("sweeps_computed", C.c_int64),
     ]
 
 
@@ -94,6 +94,7 @@ SIGNATURES = {
     "ldopf_get_structure": (C.c_int, [C.c_void_p, _i64, C.c_int64, _i64, C.c_int64]),
     "ldopf_get_history": (C.c_int, [C.c_void_p, _d, C.c_int64, _i64]),
     "ldopf_get_operators": (C.c_int, [C.c_void_p, _d, C.c_int64, _d, C.c_int64, _i32, C.c_int64]),
+    "ldopf_get_phase_times": (C.c_int, [C.c_void_p, _d]),
     "ldopf_objective": (C.c_int, [C.c_void_p, _d]),
     "ldopf_get_global_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "ldopf_get_local_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),

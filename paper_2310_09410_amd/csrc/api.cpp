@@ -73,7 +73,9 @@ struct ldopf_problem {
     bool have_x = false;
     uint64_t spin_limit = 0;
 
-    DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart;
+    DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart, prof;
+    double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double tick_ms = 1e-5;  // wall-clock tick in ms
     DevBuf<int32_t> ns, ms, rank_d, flags;
     DevBuf<int64_t> a_off, row_off, loc_off, basis_off;
     DevBuf<PartInfo> parts;
@@ -123,6 +125,7 @@ void check_options(const ldopf_options& o) {
     if (o.residual_form != LDOPF_RESIDUAL_PAPER) fail(LDOPF_INVALID_ARGUMENT, "unknown residual form");
     if (o.check_termination != 0 && o.check_termination != 1) fail(LDOPF_INVALID_ARGUMENT, "check_termination must be 0 or 1");
     if (o.history != 0 && o.history != 1) fail(LDOPF_INVALID_ARGUMENT, "history must be 0 or 1");
+    if (o.profile != 0 && o.profile != 1) fail(LDOPF_INVALID_ARGUMENT, "profile must be 0 or 1");
     if (o.rows_per_part < 0) fail(LDOPF_INVALID_ARGUMENT, "rows_per_part must be >= 0");
     if (o.block_threads != 0 && (o.block_threads < 64 || o.block_threads > 1024 || o.block_threads % 64))
         fail(LDOPF_INVALID_ARGUMENT, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
@@ -157,6 +160,7 @@ void build_device(ldopf_problem& h) {
     if (lds_optin <= 0) hip_check(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device attribute");
     // a barrier wait longer than 5 s means the launch is broken
     h.spin_limit = uint64_t(std::max(clock_khz, 1000)) * 1000ull * 5ull;
+    h.tick_ms = 1.0 / double(std::max(clock_khz, 1));
 
     for (int32_t n : lp.ns)
         if (n > 255) fail(LDOPF_UNSUPPORTED, "subsystems with more than 255 variables are not supported on the device");
@@ -214,6 +218,7 @@ void build_device(ldopf_problem& h) {
 
     h.plan = make_plan(lp, h.rank, h.fp32, h.opts.rows_per_part, h.opts.block_threads, cus, lds_optin);
     const Plan& pl = h.plan;
+    if (pl.n_parts > kMaxParts) fail(LDOPF_UNSUPPORTED, "too many workgroups for the grid barrier");
     hip_check(prepare_sweep(h.fp32, size_t(pl.lds_bytes)), "sweep LDS attribute");
     int per_cu = 0;
     hip_check(sweep_occupancy(h.fp32, pl.block_threads, size_t(pl.lds_bytes), &per_cu), "sweep occupancy");
@@ -246,8 +251,9 @@ void build_device(ldopf_problem& h) {
     h.x.alloc(lp.n, "x");
     h.bpart.alloc(size_t(2) * std::max(pl.n_slots, 1) * (h.fp32 ? 4 : 8), "boundary slots");
     h.rpart.alloc(size_t(2) * pl.n_parts * 8, "residual slots");
-    h.bar.alloc(128, "barrier");
+    h.bar.alloc(kBarWords, "barrier");
     h.st.alloc(1, "status");
+    h.prof.alloc(8, "phase times");
     init_state(h);
 }
 
@@ -291,6 +297,7 @@ SweepArgs<T> sweep_args(ldopf_problem& h) {
     a.check = h.opts.check_termination;
     a.P = h.plan.n_parts;
     a.spin_limit = h.spin_limit;
+    a.prof = h.opts.profile ? h.prof.p : nullptr;
     return a;
 }
 
@@ -512,6 +519,12 @@ int ldopf_solve(ldopf_problem* h, ldopf_status* status) {
         float ms = 0.f;
         hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1), "event time");
         h->last_sweep_ms = ms;
+        std::fill(h->phase_ms, h->phase_ms + 8, 0.0);
+        if (h->opts.profile) {
+            double ticks[8];
+            hip_check(hipMemcpy(ticks, h->prof.p, sizeof(ticks), hipMemcpyDeviceToHost), "download phase times");
+            for (int i = 0; i < 8; ++i) h->phase_ms[i] = ticks[i] * h->tick_ms;
+        }
         h->hist_len = h->opts.history ? std::min<int64_t>(st.iters, int64_t(h->hist.count / 4)) : 0;
         if (st.iters > 0) h->have_x = true;
         if (st.flags & 1) fail(LDOPF_DEVICE_ERROR, "grid barrier wait timed out in the sweep kernel");
@@ -524,6 +537,7 @@ int ldopf_solve(ldopf_problem* h, ldopf_status* status) {
             status->eps_dual = st.eps_d;
             status->sweep_ms = ms;
             status->precompute_ms = h->precompute_ms;
+            status->sweeps_computed = st.computed;
         }
         if (st.flags & 2) {
             code = LDOPF_NUMERICAL;
@@ -626,6 +640,14 @@ int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t cap_abar, 
             std::memcpy(rank, h->rank.data(), h->lp.S * 4);
         }
         hip_check(hipStreamSynchronize(h->stream), "download operators");
+    });
+}
+
+int ldopf_get_phase_times(const ldopf_problem* h, double* ms) {
+    return guard([&] {
+        need(h, "handle");
+        need(ms, "ms");
+        std::memcpy(ms, h->phase_ms, sizeof(h->phase_ms));
     });
 }
 

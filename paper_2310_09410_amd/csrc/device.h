@@ -28,8 +28,16 @@ struct PrecomputeArgs {
     double tol_rhs; // ... and then its right-hand side must be below tol_rhs * (1 + max |b_s|)
 };
 
+// Grid barrier words: [0] top arrival counter, [64] generation, then one
+// counter per group of kBarGroup workgroups at kBarGroupBase + 64 * group.
+constexpr unsigned kBarGroup = 16;
+constexpr unsigned kBarGroupBase = 128;
+constexpr int kBarWords = 16384;
+constexpr int kMaxParts = int((kBarWords - kBarGroupBase) / 64) * int(kBarGroup);
+
 struct SweepStatus {
-    int64_t iters;
+    int64_t iters;     // sweep whose state is returned
+    int64_t computed;  // sweeps computed (the test of a sweep is read during the next one)
     int32_t converged;
     int32_t flags;  // 1: barrier wait timed out, 2: non-finite residuals
     double pres, dres, eps_p, eps_d;
@@ -72,6 +80,7 @@ struct SweepArgs {
     int32_t check;
     int32_t P;
     uint64_t spin_limit; // wall-clock ticks a barrier may wait
+    double* prof;        // nullable: per-phase wall-clock ticks of workgroup 0 (8 entries)
 };
 
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream);

@@ -44,6 +44,49 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// DPP lane moves (gfx9 encodings): quad_perm [1,0,3,2] swaps neighbours,
+// quad_perm [2,3,0,1] swaps pairs, row_half_mirror reverses each group of 8,
+// row_mirror reverses each row of 16.
+constexpr int kDppXor1 = 0xB1;
+constexpr int kDppXor2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over aligned groups of g lanes (g = 1, 2, 4, 8, 16); every lane of a
+// group ends with the same bits. Needs every lane of the wave active.
+template <typename T>
+__device__ inline T group_sum(T v, int g) {
+    if (g >= 2) v += dpp_move<kDppXor1>(v);
+    if (g >= 4) v += dpp_move<kDppXor2>(v);
+    if (g >= 8) v += dpp_move<kDppHalfMirror>(v);
+    if (g >= 16) v += dpp_move<kDppMirror>(v);
+    return v;
+}
+
+__device__ inline double read_lane(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes of a wave without LDS traffic: row sums by DPP, then
+// the four row sums in a fixed order. The result is wave-uniform and the same
+// on every wave given the same inputs. Needs every lane of the wave active.
+__device__ inline double wave_total(double v) {
+    v = group_sum(v, 16);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 __device__ inline void st_agent(double* p, double v) {
     __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -228,22 +271,36 @@ struct SubLds {
 static_assert(sizeof(SubLds) == 16, "SubLds layout");
 
 // Grid-wide barrier over the co-resident workgroups of a cooperative launch.
-// Thread 0 arrives with an acquire-release add on the arrival counter; the
-// last arriver resets it and publishes the new generation with a release
-// store. Waiting is bounded by a wall-clock limit so that a broken launch
-// ends instead of hanging; the caller sees the failure in the return value.
-__device__ inline bool grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks, unsigned& epoch,
-                                    uint64_t limit, int* ok_lds) {
+// Arrivals are split over groups of kBarGroup workgroups, each with its own
+// counter on its own cache line, so that no more than kBarGroup atomics hit
+// one address per barrier; the last arriver of a group arrives at the top
+// counter, and the last arriver there publishes the new generation. Every
+// wait is bounded by a wall-clock limit so that a broken launch ends instead
+// of hanging; the caller sees the failure in the return value.
+__device__ inline bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& epoch, uint64_t limit, int* ok_lds) {
     __syncthreads();
     if (threadIdx.x == 0) {
         ++epoch;
         int ok = 1;
         if (nblocks > 1) {
-            const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev == nblocks - 1) {
-                __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
+            const unsigned g = blockIdx.x / kBarGroup;
+            const unsigned ngroups = (nblocks + kBarGroup - 1) / kBarGroup;
+            const unsigned gsize = min(kBarGroup, nblocks - g * kBarGroup);
+            unsigned* top = bar;
+            unsigned* gen = bar + 64;
+            unsigned* gc = bar + kBarGroupBase + 64 * g;
+            bool released = false;
+            const unsigned prev = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == gsize - 1) {
+                __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned p2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                if (p2 == ngroups - 1) {
+                    __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    released = true;
+                }
+            }
+            if (!released) {
                 const uint64_t t0 = wall_clock64();
                 while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
                     __builtin_amdgcn_s_sleep(1);
@@ -261,9 +318,17 @@ __device__ inline bool grid_barrier(unsigned* count, unsigned* gen, unsigned nbl
     return *ok_lds != 0;
 }
 
+// Lanes per (subsystem, basis row) task of t = W v: as many as the
+// workgroup can give, up to 8, so that long rows do not serialize.
+__device__ inline int task_lanes(int tasks, int threads) {
+    int g = 1;
+    while (g < 8 && tasks * g * 2 <= threads) g <<= 1;
+    return g;
+}
+
 }  // namespace
 
-template <typename T>
+template <typename T, bool PROF>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int bar_ok;
@@ -275,9 +340,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     T* bbar = reinterpret_cast<T*>(smem + L.bbar);
     T* xs[2] = {reinterpret_cast<T*>(smem + L.xs0), reinterpret_cast<T*>(smem + L.xs1)};
     T* lam[2] = {reinterpret_cast<T*>(smem + L.lam0), reinterpret_cast<T*>(smem + L.lam1)};
+    T* xl[2] = {reinterpret_cast<T*>(smem + L.xloc0), reinterpret_cast<T*>(smem + L.xloc1)};
     T* vb = reinterpret_cast<T*>(smem + L.v);
     T* tb = reinterpret_cast<T*>(smem + L.t);
-    T* xloc = reinterpret_cast<T*>(smem + L.xloc);
     T* ownp = reinterpret_cast<T*>(smem + L.ownp);
     T* crho = reinterpret_cast<T*>(smem + L.crho);
     T* vlo = reinterpret_cast<T*>(smem + L.lo);
@@ -298,6 +363,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     const T rho = T(a.rho);
     const T irho = T(1.0 / a.rho);
     const int R = pi.n_row, V = pi.n_var, TK = pi.n_tk;
+    const unsigned P = unsigned(a.P);
+    const int64_t ns = a.n_slots;
 
     // ---- load this part into LDS
     for (int i = tid; i < pi.n_sub; i += nt) {
@@ -319,7 +386,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         crho[v] = T(a.c[g] / a.rho);
         vlo[v] = T(a.lo[g]);
         vhi[v] = T(a.hi[g]);
-        vcnt[v] = T(a.cnt[g]);
+        vcnt[v] = T(1.0 / a.cnt[g]);  // reciprocal of the copy count N_i
         slo[v] = a.var_slot_lo[pi.var_begin + v];
         shi[v] = a.var_slot_hi[pi.var_begin + v];
         sown[v] = a.var_slot[pi.var_begin + v];
@@ -336,7 +403,6 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     __syncthreads();
 
     // ---- partial sums of the starting state for the first global update
-    const int64_t ns = a.n_slots;
     for (int v = tid; v < V; v += nt) {
         T acc = T(0);
         for (int q = coff[v]; q < coff[v + 1]; ++q) {
@@ -346,49 +412,124 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         ownp[v] = acc;
         if (sown[v] >= 0) st_agent(a.bpart + sown[v], acc);
     }
-    // every wave's published stores complete before its workgroup arrives
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // every wave's device-scope stores are complete before its workgroup arrives
+    __builtin_amdgcn_s_waitcnt(0);
     unsigned epoch = 0;
-    const unsigned P = unsigned(a.P);
-    bool ok = grid_barrier(a.bar, a.bar + 64, P, epoch, a.spin_limit, &bar_ok);
+    bool ok = grid_barrier(a.bar, P, epoch, a.spin_limit, &bar_ok);
 
-    int64_t done = 0;
-    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0, d4 = 0.0;
+    const int GA = task_lanes(TK, nt);
+    // residual partial sums of the previous sweep, loaded one sweep ahead of
+    // their use (wave 0, lane l holds the parts l, l + 64, l + 128, l + 192)
+    double pv[4][5];
+    auto issue_partials = [&](int par) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned p = unsigned(lane) + 64u * u;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) pv[u][q] = p < P ? ld_agent(a.rpart + (int64_t(par) * P + p) * 8 + q) : 0.0;
+        }
+    };
+    uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t tlast = 0;
+    auto stamp = [&](int ph) {
+        if (PROF && blockIdx.x == 0 && tid == 0) {
+            const uint64_t now = wall_clock64();
+            tprof[ph] += now - tlast;
+            tlast = now;
+        }
+    };
+    if (PROF && blockIdx.x == 0 && tid == 0) tlast = wall_clock64();
+
+    int64_t done = 0;     // sweeps computed
+    int64_t result = 0;   // sweep whose state is returned
     int converged = 0, nonfinite = 0;
+    double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const double sq = sqrt(double(a.nloc));
+    // termination test of one finished sweep from the grid-wide sums held in pv
+    auto decide = [&](int64_t sweep) -> bool {
+        if (wv == 0) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const double acc = wave_total(pv[0][q] + pv[1][q] + pv[2][q] + pv[3][q]);
+                if (lane == 0) tot[q] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 5; ++q) d[q] = tot[q];
+        const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
+        const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
+        const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
+        if (blockIdx.x == 0 && tid == 0 && sweep <= a.hist_cap) {
+            double* h = a.hist + (sweep - 1) * 4;
+            h[0] = pres;
+            h[1] = dres;
+            h[2] = eps_p;
+            h[3] = eps_d;
+        }
+        nonfinite = !isfinite(d[0] + d[1] + d[2] + d[3] + d[4]);
+        converged = pres <= eps_p && dres <= eps_d;
+        return nonfinite || (a.check && converged);
+    };
+
+    bool stopped = false;
     while (ok && done < a.max_iter) {
         const int cur = int(done & 1), nx = cur ^ 1;
         const T* bcur = a.bpart + int64_t(cur) * ns;
         T* bnx = a.bpart + int64_t(nx) * ns;
+        T* xg = xl[nx];
         // closed_1: clipped average of the copies
         for (int v = tid; v < V; v += nt) {
             T s;
             if (slo[v] < 0) {
                 s = ownp[v];
             } else {
-                s = T(0);
-                for (int q = slo[v]; q < shi[v]; ++q) s += ld_agent(bcur + q);
+                // all owners' slots in owner order; loads issued together
+                const int q0 = slo[v], q1 = shi[v];
+                T b0 = ld_agent(bcur + q0);
+                T b1 = q0 + 1 < q1 ? ld_agent(bcur + q0 + 1) : T(0);
+                T b2 = q0 + 2 < q1 ? ld_agent(bcur + q0 + 2) : T(0);
+                T b3 = q0 + 3 < q1 ? ld_agent(bcur + q0 + 3) : T(0);
+                s = b0 + b1;
+                if (q0 + 2 < q1) s += b2;
+                if (q0 + 3 < q1) s += b3;
+                for (int q = q0 + 4; q < q1; ++q) s += ld_agent(bcur + q);
             }
-            T xv = (s - crho[v]) / vcnt[v];
+            T xv = (s - crho[v]) * vcnt[v];
             xv = xv < vlo[v] ? vlo[v] : xv;
             xv = xv > vhi[v] ? vhi[v] : xv;
-            xloc[v] = xv;
+            xg[v] = xv;
         }
         __syncthreads();
+        stamp(0);
         // v = B_s x + lambda_s / rho
         const T* lc = lam[cur];
-        for (int r = tid; r < R; r += nt) vb[r] = xloc[rlv[r]] + lc[r] * irho;
+        for (int r = tid; r < R; r += nt) vb[r] = xg[rlv[r]] + lc[r] * irho;
         __syncthreads();
-        // t = W v, one task per (subsystem, basis row)
-        for (int q = tid; q < TK; q += nt) {
-            const SubLds m = meta[tks[q]];
-            const int k = q - m.t0;
-            const T* wr = W + m.w0 + k * m.n;
-            const T* vv = vb + m.row0;
+        stamp(1);
+        // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
+        for (int base = 0; base < TK * GA; base += nt) {
+            const int q0 = base + tid;
+            const int task = q0 / GA, sub = q0 - task * GA;
             T acc = T(0);
-            for (int j = 0; j < m.n; ++j) acc += wr[j] * vv[j];
-            tb[q] = acc;
+            if (task < TK) {
+                const SubLds m = meta[tks[task]];
+                const T* wr = W + m.w0 + (task - m.t0) * m.n;
+                const T* vv = vb + m.row0;
+                T acc1 = T(0);
+                int j = sub;
+                for (; j + GA < m.n; j += 2 * GA) {
+                    acc += wr[j] * vv[j];
+                    acc1 += wr[j + GA] * vv[j + GA];
+                }
+                if (j < m.n) acc += wr[j] * vv[j];
+                acc += acc1;
+            }
+            acc = group_sum(acc, GA);
+            if (task < TK && sub == 0) tb[task] = acc;
         }
         __syncthreads();
+        stamp(2);
         // closed_2 in rank form, then ADMM-3; residual sums in FP64
         double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
         const T* xc = xs[cur];
@@ -397,11 +538,19 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         for (int r = tid; r < R; r += nt) {
             const SubLds m = meta[rsub[r]];
             const int j = r - m.row0;
-            T acc = T(0);
-            for (int k = 0; k < m.k; ++k) acc += W[m.w0 + k * m.n + j] * tb[m.t0 + k];
+            const T* wc = W + m.w0 + j;
+            const T* tt = tb + m.t0;
+            T acc = T(0), acc1 = T(0);
+            int k = 0;
+            for (; k + 1 < m.k; k += 2) {
+                acc += wc[k * m.n] * tt[k];
+                acc1 += wc[(k + 1) * m.n] * tt[k + 1];
+            }
+            if (k < m.k) acc += wc[k * m.n] * tt[k];
+            acc += acc1;
             const T vr = vb[r];
             const T y = m.mode ? bbar[r] + (vr - acc) : bbar[r] + acc;
-            const T z = xloc[rlv[r]];
+            const T z = xg[rlv[r]];
             const T lnew = lc[r] + rho * (z - y);
             xn[r] = y;
             ln[r] = lnew;
@@ -413,11 +562,11 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             p3 += double(y) * double(y);
             p4 += double(lnew) * double(lnew);
         }
-        p0 = wave_sum(p0);
-        p1 = wave_sum(p1);
-        p2 = wave_sum(p2);
-        p3 = wave_sum(p3);
-        p4 = wave_sum(p4);
+        p0 = wave_total(p0);
+        p1 = wave_total(p1);
+        p2 = wave_total(p2);
+        p3 = wave_total(p3);
+        p4 = wave_total(p4);
         if (lane == 0) {
             red[wv * 8 + 0] = p0;
             red[wv * 8 + 1] = p1;
@@ -426,6 +575,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             red[wv * 8 + 4] = p4;
         }
         __syncthreads();
+        stamp(3);
         // partial sums for the next global update; publish boundary slots
         for (int v = tid; v < V; v += nt) {
             T acc = T(0);
@@ -441,69 +591,56 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             for (int w = 0; w < nw; ++w) acc += red[w * 8 + tid];
             st_agent(a.rpart + (int64_t(nx) * P + blockIdx.x) * 8 + tid, acc);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        ok = grid_barrier(a.bar, a.bar + 64, P, epoch, a.spin_limit, &bar_ok);
+        __builtin_amdgcn_s_waitcnt(0);
+        stamp(4);
+        ok = grid_barrier(a.bar, P, epoch, a.spin_limit, &bar_ok);
+        stamp(5);
         if (!ok) break;
-        // termination test (Section III-C) from the grid-wide sums, computed
-        // the same way by every workgroup
-        if (wv == 0) {
-            for (int q = 0; q < 5; ++q) {
-                double acc = 0.0;
-                for (unsigned p = lane; p < P; p += 64) acc += ld_agent(a.rpart + (int64_t(nx) * P + p) * 8 + q);
-                acc = wave_sum(acc);
-                if (lane == 0) tot[q] = acc;
-            }
-        }
-        __syncthreads();
-        d0 = tot[0];
-        d1 = tot[1];
-        d2 = tot[2];
-        d3 = tot[3];
-        d4 = tot[4];
         ++done;
-        const double pres = sqrt(d0), dres = a.rho * sqrt(d1);
-        const double sq = sqrt(double(a.nloc));
-        const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d2), sqrt(d3));
-        const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d4);
-        if (blockIdx.x == 0 && tid == 0 && done <= a.hist_cap) {
-            double* h = a.hist + (done - 1) * 4;
-            h[0] = pres;
-            h[1] = dres;
-            h[2] = eps_p;
-            h[3] = eps_d;
+        // the test of the previous sweep, from sums loaded during this one
+        if (done >= 2 && decide(done - 1)) {
+            result = done - 1;
+            stopped = true;
+            break;
         }
-        nonfinite = !isfinite(d0 + d1 + d2 + d3 + d4);
-        converged = pres <= eps_p && dres <= eps_d;
-        if (nonfinite || (a.check && converged)) break;
+        if (wv == 0) issue_partials(int(done & 1));
+        stamp(6);
     }
-    // ---- write the state back (canonical order, FP64)
-    const int fp = int(done & 1);
+    if (ok && !stopped) {
+        // the last computed sweep (max_iter reached): its sums are in flight
+        result = done;
+        if (done > 0) decide(done);
+    }
+    // ---- write the state of sweep `result` back (canonical order, FP64)
+    const int fp = int(result & 1);
     for (int r = tid; r < R; r += nt) {
         const int canon = a.row_canon[pi.row_begin + r];
         a.xs[canon] = double(xs[fp][r]);
         a.lam[canon] = double(lam[fp][r]);
     }
-    if (done > 0)
+    if (result > 0)
         for (int v = tid; v < V; v += nt)
-            if (a.var_writer[pi.var_begin + v]) a.x[a.var_gid[pi.var_begin + v]] = double(xloc[v]);
+            if (a.var_writer[pi.var_begin + v]) a.x[a.var_gid[pi.var_begin + v]] = double(xl[fp][v]);
     if (tid == 0 && (!ok || nonfinite)) atomicOr(&a.st->flags, (ok ? 0 : 1) | (nonfinite ? 2 : 0));
     if (blockIdx.x == 0 && tid == 0) {
-        a.st->iters = done;
+        a.st->iters = result;
+        a.st->computed = done;
         a.st->converged = converged;
-        a.st->pres = sqrt(d0);
-        a.st->dres = a.rho * sqrt(d1);
-        const double sq = sqrt(double(a.nloc));
-        a.st->eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d2), sqrt(d3));
-        a.st->eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d4);
+        a.st->pres = sqrt(d[0]);
+        a.st->dres = a.rho * sqrt(d[1]);
+        a.st->eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
+        a.st->eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
+        if (PROF && a.prof)
+            for (int i = 0; i < 8; ++i) a.prof[i] = double(tprof[i]);
     }
 }
 
-__global__ void reset_sync_kernel(unsigned* bar, SweepStatus* st) {
-    // plain stores; run on the same stream before every sweep launch
-    const int t = threadIdx.x;
-    if (t < 128) bar[t] = 0u;
-    if (t == 0) {
+__global__ void reset_sync_kernel(unsigned* bar, int words, SweepStatus* st) {
+    // plain stores; runs on the same stream before every sweep launch
+    for (int t = threadIdx.x; t < words; t += blockDim.x) bar[t] = 0u;
+    if (threadIdx.x == 0) {
         st->iters = 0;
+        st->computed = 0;
         st->converged = 0;
         st->flags = 0;
         st->pres = st->dres = st->eps_p = st->eps_d = 0.0;
@@ -519,36 +656,41 @@ hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool PROF>
 static const void* sweep_ptr() {
-    return reinterpret_cast<const void*>(&sweep_kernel<T>);
+    return reinterpret_cast<const void*>(&sweep_kernel<T, PROF>);
 }
 
 hipError_t prepare_sweep(bool fp32, size_t lds_bytes) {
-    const void* f = fp32 ? sweep_ptr<float>() : sweep_ptr<double>();
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+    for (const void* f : {fp32 ? sweep_ptr<float, false>() : sweep_ptr<double, false>(),
+                          fp32 ? sweep_ptr<float, true>() : sweep_ptr<double, true>()}) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu) {
-    const void* f = fp32 ? sweep_ptr<float>() : sweep_ptr<double>();
+    const void* f = fp32 ? sweep_ptr<float, false>() : sweep_ptr<double, false>();
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 
 template <typename T>
-static hipError_t launch_sweep_t(SweepArgs<T> a, int grid, int block, size_t lds, unsigned* bar, SweepStatus* st,
-                                 hipStream_t stream) {
-    hipLaunchKernelGGL(reset_sync_kernel, dim3(1), dim3(128), 0, stream, bar, st);
+static hipError_t launch_sweep_t(const SweepArgs<T>& a, int grid, int block, size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_sync_kernel, dim3(1), dim3(256), 0, stream, a.bar, kBarWords, a.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    void* args[] = {&a};
-    return hipLaunchCooperativeKernel(sweep_ptr<T>(), dim3(grid), dim3(block), args, unsigned(lds), stream);
+    SweepArgs<T> copy = a;
+    void* args[] = {&copy};
+    const void* f = a.prof ? sweep_ptr<T, true>() : sweep_ptr<T, false>();
+    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), args, unsigned(lds), stream);
 }
 
 hipError_t launch_sweep(const SweepArgs<double>& a, int grid, int block, size_t lds, hipStream_t stream) {
-    return launch_sweep_t<double>(a, grid, block, lds, a.bar, a.st, stream);
+    return launch_sweep_t<double>(a, grid, block, lds, stream);
 }
 hipError_t launch_sweep(const SweepArgs<float>& a, int grid, int block, size_t lds, hipStream_t stream) {
-    return launch_sweep_t<float>(a, grid, block, lds, a.bar, a.st, stream);
+    return launch_sweep_t<float>(a, grid, block, lds, stream);
 }
 
 }  // namespace ldopf

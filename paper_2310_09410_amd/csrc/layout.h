@@ -14,7 +14,7 @@
 namespace ldopf {
 
 struct LdsLayout {
-    uint32_t W, bbar, xs0, xs1, lam0, lam1, v, t, xloc, ownp, crho, lo, hi, cnt;  // T arrays
+    uint32_t W, bbar, xs0, xs1, lam0, lam1, v, t, xloc0, xloc1, ownp, crho, lo, hi, cnt;  // T arrays
     uint32_t slot_lo, slot_hi, slot_own;                                         // int32 per var
     uint32_t row_lvar, row_sub, copy_off, copy_rows, tk_sub, meta;                // index arrays
     uint32_t red;                                                                // double [waves][8]
@@ -41,7 +41,8 @@ LDOPF_HD inline LdsLayout lds_layout(uint32_t w, uint32_t w_words, uint32_t rows
     L.lam1 = take(w * rows);
     L.v = take(w * rows);
     L.t = take(w * tks);
-    L.xloc = take(w * vars);
+    L.xloc0 = take(w * vars);
+    L.xloc1 = take(w * vars);
     L.ownp = take(w * vars);
     L.crho = take(w * vars);
     L.lo = take(w * vars);

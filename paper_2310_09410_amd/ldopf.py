@@ -177,6 +177,11 @@ class Problem:
                                            bb.shape[0], _ptr(rk, C.c_int32), rk.shape[0]), "ldopf_get_operators")
         return ab, bb, rk
 
+    def get_phase_times(self) -> np.ndarray:
+        ms = np.zeros(8)
+        _check(N.lib().ldopf_get_phase_times(self.h, _ptr(ms, C.c_double)), "ldopf_get_phase_times")
+        return ms
+
     def objective(self) -> float:
         f = C.c_double(0.0)
         _check(N.lib().ldopf_objective(self.h, C.byref(f)), "ldopf_objective")
