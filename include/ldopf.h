@@ -276,6 +276,136 @@ LDOPF_API int ldopf_get_global_device(const ldopf_problem* h, double* x_device, 
 LDOPF_API int ldopf_get_local_device(const ldopf_problem* h, double* xs_device, double* lam_device,
                                      int64_t cap);
 
+/* ------------------------------------------------------------------------
+ * Batched scenarios: one network, B load scenarios solved together.
+ *
+ * Scenario k multiplies the reference powers a, b of every load l by
+ * load_scale[k * n_load + l]. For a voltage-dependent load that also scales
+ * the squared-voltage coefficient of its model rows (VDLM-1, VDLM-2), so only
+ * subsystems without such loads share one operator Abar_s across scenarios;
+ * their local update (closed_2) for all scenarios is one small GEMM on the
+ * matrix cores. Every scenario runs Algorithm 1 on its own: its own global
+ * update, dual update and termination test (Section III-C), and it keeps the
+ * state of its first sweep that passes the test while the others continue.
+ * Sweeps run in the FP32-mixed form: operators are precomputed in FP64 and
+ * stored in FP32; residual sums and the test are FP64. */
+typedef struct ldopf_batch ldopf_batch;
+
+typedef struct ldopf_batch_status {
+    int64_t sweeps;       /* sweeps the batch ran: its slowest scenario's count, or max_iter */
+    int32_t n_scen;
+    int32_t n_converged;
+    int32_t n_numerical;  /* scenarios stopped by NaN or Inf */
+    int32_t code;         /* LDOPF_OK, LDOPF_NOT_CONVERGED or LDOPF_NUMERICAL */
+    double solve_ms;      /* device time of the solve (HIP events on the batch's stream) */
+    double precompute_ms; /* device time of the operator precompute of all scenarios */
+} ldopf_batch_status;
+
+typedef struct ldopf_batch_sizes {
+    int64_t n, n_sub, n_local;
+    int32_t n_scen, n_scen_padded;          /* scenarios, padded to a multiple of 64 */
+    int64_t n_mfma_subsystems;              /* shared operator, GEMM on matrix cores */
+    int64_t n_vector_subsystems;            /* per-scenario operator, rank form */
+    int64_t scenario_operator_words;        /* FP32 words of per-scenario operators */
+    int64_t shared_operator_words;          /* FP32 words of shared operators */
+    int32_t rows_per_chunk, waves_per_tile; /* tuning of the local update */
+    int32_t graph_sweeps;                   /* sweeps per captured HIP graph */
+    int32_t pad;
+} ldopf_batch_sizes;
+
+/* Assemble the network, precompute every (subsystem, scenario) operator on
+ * the device and set every scenario to the initial point of Section V-A.
+ * load_scale: [n_scen x n_load] row-major host array (finite; nullable when
+ * n_load = 0). 1 <= n_scen <= 1024. opts->precision must be
+ * LDOPF_FP32_MIXED (else LDOPF_UNSUPPORTED); rho is fixed at creation;
+ * rows_per_part sets the rows per chunk of the local update (0: 256). The
+ * batch runs on a stream of its own, ordered after the caller's stream. */
+LDOPF_API int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* load_scale,
+                                 const ldopf_options* opts, void* stream, ldopf_batch** out);
+LDOPF_API int ldopf_batch_destroy(ldopf_batch* h);
+/* Replace eps_rel, eps_abs, max_iter, check_termination (rho and precision fixed). */
+LDOPF_API int ldopf_batch_set_options(ldopf_batch* h, const ldopf_options* opts);
+/* Every scenario back to the initial point. */
+LDOPF_API int ldopf_batch_reset(ldopf_batch* h);
+/* Run until every scenario stopped or max_iter sweeps; blocks until done. */
+LDOPF_API int ldopf_batch_solve(ldopf_batch* h, ldopf_batch_status* status);
+/* One scenario's iterations (its stopping sweep), converged flag and last residuals. */
+LDOPF_API int ldopf_batch_get_scenario(const ldopf_batch* h, int32_t scen, ldopf_status* status);
+/* One scenario's global x [n] and local x_s, lambda [N_loc] (either nullable), as FP64. */
+LDOPF_API int ldopf_batch_get_global(const ldopf_batch* h, int32_t scen, double* x, int64_t cap);
+LDOPF_API int ldopf_batch_get_local(const ldopf_batch* h, int32_t scen, double* xs, double* lam, int64_t cap);
+LDOPF_API int ldopf_batch_get_sizes(const ldopf_batch* h, ldopf_batch_sizes* out);
+/* Autotuner: time short runs of the local update over rows per chunk and
+ * waves per scenario tile, keep the fastest, and remember it in a text cache
+ * file keyed by device, network shape and batch size (cache_path nullable:
+ * no cache). Resets the batch. Results do not depend on the choice except
+ * for the summation order of the residual sums. */
+LDOPF_API int ldopf_batch_tune(ldopf_batch* h, const char* cache_path, int32_t* rows_per_chunk,
+                               int32_t* waves_per_tile);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop for OPF solves of differing feeders.
+ *
+ * Requests are assembled at submit (network errors are returned at once) and
+ * queued. A scheduler thread admits queued requests first-fit in arrival
+ * order when a stream slot is free, the request's device bytes fit the HBM
+ * budget beside the requests in flight, and its sweep's workgroups fit the
+ * chip beside the sweeps running; the oldest request is not overtaken more
+ * than 64 times. Admitted requests have their operators precomputed and their
+ * solve (Algorithm 1 to the termination test) launched on their slot's
+ * stream; their state stays resident until they finish, and several run on
+ * the device at once. Results are copied to host memory at completion and the
+ * device memory is released. Latency = completion - submit. Every call is
+ * thread-safe. A result does not depend on what else runs beside it. */
+typedef struct ldopf_server ldopf_server;
+
+typedef enum ldopf_request_state {
+    LDOPF_REQ_QUEUED = 0,
+    LDOPF_REQ_RUNNING = 1,
+    LDOPF_REQ_DONE = 2,   /* solved (converged or max_iter reached); results available */
+    LDOPF_REQ_FAILED = 3  /* error, cancelled, or dropped at shutdown */
+} ldopf_request_state;
+
+typedef struct ldopf_server_stats {
+    int64_t submitted, completed, failed, queued, running;
+    int64_t peak_running;
+    int64_t bytes_in_use, peak_bytes_in_use, budget_bytes;
+    double p50_ms, p99_ms, mean_ms, max_ms; /* latency of completed requests (nearest rank) */
+    double wall_s;        /* first submit to last completion */
+    double solves_per_s;  /* completed / wall_s */
+} ldopf_server_stats;
+
+/* Host-only: the device bytes a request would hold at its peak and the
+ * workgroups of its sweep (planned assuming full row rank), as the server's
+ * admission counts them. */
+LDOPF_API int ldopf_request_estimate(const ldopf_network* net, const ldopf_options* opts, int64_t* bytes,
+                                     int32_t* workgroups);
+
+/* hbm_budget_bytes <= 0: 80% of the free device memory. 1 <= max_slots <= 64
+ * streams (requests in flight at once). */
+LDOPF_API int ldopf_server_create(int64_t hbm_budget_bytes, int32_t max_slots, ldopf_server** out);
+/* Copy and queue one request; LDOPF_OUT_OF_MEMORY when it alone exceeds the
+ * budget. opts: as for ldopf_create (history is not recorded). */
+LDOPF_API int ldopf_server_submit(ldopf_server* srv, const ldopf_network* net, const ldopf_options* opts,
+                                  int64_t* req_id);
+/* Current state (ldopf_request_state) and, once done, the solve status. */
+LDOPF_API int ldopf_server_poll(ldopf_server* srv, int64_t req_id, int32_t* state, ldopf_status* status);
+/* Block until the request is done or failed or timeout_s passed (< 0: no
+ * limit); returns the request's error code when it failed. */
+LDOPF_API int ldopf_server_wait(ldopf_server* srv, int64_t req_id, double timeout_s, int32_t* state,
+                                ldopf_status* status);
+/* Remove a queued request (it becomes FAILED with LDOPF_INVALID_ARGUMENT). */
+LDOPF_API int ldopf_server_cancel(ldopf_server* srv, int64_t req_id);
+/* Results of a done request: x [n], x_s and lambda [N_loc] (each nullable);
+ * sizes (nullable) receives n and N_loc. */
+LDOPF_API int ldopf_server_fetch(ldopf_server* srv, int64_t req_id, double* x, int64_t cap_x, double* xs,
+                                 double* lam, int64_t cap_local, int64_t sizes[2]);
+/* Forget a finished request and its host-side results. */
+LDOPF_API int ldopf_server_release(ldopf_server* srv, int64_t req_id);
+LDOPF_API int ldopf_server_get_stats(ldopf_server* srv, ldopf_server_stats* stats);
+/* Drop queued requests, wait for running ones, stop the scheduler. */
+LDOPF_API int ldopf_server_destroy(ldopf_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

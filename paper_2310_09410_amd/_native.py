@@ -74,6 +74,36 @@ class ldopf_status(C.Structure):
     ]
 
 
+class ldopf_batch_status(C.Structure):
+    _fields_ = [
+        ("sweeps", C.c_int64), ("n_scen", C.c_int32), ("n_converged", C.c_int32), ("n_numerical", C.c_int32),
+        ("code", C.c_int32), ("solve_ms", C.c_double), ("precompute_ms", C.c_double),
+    ]
+
+
+class ldopf_batch_sizes(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("n_sub", C.c_int64), ("n_local", C.c_int64), ("n_scen", C.c_int32),
+        ("n_scen_padded", C.c_int32), ("n_mfma_subsystems", C.c_int64), ("n_vector_subsystems", C.c_int64),
+        ("scenario_operator_words", C.c_int64), ("shared_operator_words", C.c_int64),
+        ("rows_per_chunk", C.c_int32), ("waves_per_tile", C.c_int32), ("graph_sweeps", C.c_int32),
+        ("pad", C.c_int32),
+    ]
+
+
+class ldopf_server_stats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("queued", C.c_int64),
+        ("running", C.c_int64), ("peak_running", C.c_int64), ("bytes_in_use", C.c_int64),
+        ("peak_bytes_in_use", C.c_int64), ("budget_bytes", C.c_int64), ("p50_ms", C.c_double),
+        ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double), ("wall_s", C.c_double),
+        ("solves_per_s", C.c_double),
+    ]
+
+
+LDOPF_REQ_QUEUED, LDOPF_REQ_RUNNING, LDOPF_REQ_DONE, LDOPF_REQ_FAILED = 0, 1, 2, 3
+
+
 # Every exported call: name -> (restype, argtypes)
 SIGNATURES = {
     "ldopf_error_string": (C.c_char_p, [C.c_int]),
@@ -98,6 +128,27 @@ SIGNATURES = {
     "ldopf_objective": (C.c_int, [C.c_void_p, _d]),
     "ldopf_get_global_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "ldopf_get_local_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "ldopf_batch_create": (C.c_int, [C.POINTER(ldopf_network), C.c_int32, _d, C.POINTER(ldopf_options), C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    "ldopf_batch_destroy": (C.c_int, [C.c_void_p]),
+    "ldopf_batch_set_options": (C.c_int, [C.c_void_p, C.POINTER(ldopf_options)]),
+    "ldopf_batch_reset": (C.c_int, [C.c_void_p]),
+    "ldopf_batch_solve": (C.c_int, [C.c_void_p, C.POINTER(ldopf_batch_status)]),
+    "ldopf_batch_get_scenario": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(ldopf_status)]),
+    "ldopf_batch_get_global": (C.c_int, [C.c_void_p, C.c_int32, _d, C.c_int64]),
+    "ldopf_batch_get_local": (C.c_int, [C.c_void_p, C.c_int32, _d, _d, C.c_int64]),
+    "ldopf_batch_get_sizes": (C.c_int, [C.c_void_p, C.POINTER(ldopf_batch_sizes)]),
+    "ldopf_batch_tune": (C.c_int, [C.c_void_p, C.c_char_p, _i32, _i32]),
+    "ldopf_request_estimate": (C.c_int, [C.POINTER(ldopf_network), C.POINTER(ldopf_options), _i64, _i32]),
+    "ldopf_server_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "ldopf_server_submit": (C.c_int, [C.c_void_p, C.POINTER(ldopf_network), C.POINTER(ldopf_options), _i64]),
+    "ldopf_server_poll": (C.c_int, [C.c_void_p, C.c_int64, _i32, C.POINTER(ldopf_status)]),
+    "ldopf_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, _i32, C.POINTER(ldopf_status)]),
+    "ldopf_server_cancel": (C.c_int, [C.c_void_p, C.c_int64]),
+    "ldopf_server_fetch": (C.c_int, [C.c_void_p, C.c_int64, _d, C.c_int64, _d, _d, C.c_int64, _i64]),
+    "ldopf_server_release": (C.c_int, [C.c_void_p, C.c_int64]),
+    "ldopf_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ldopf_server_stats)]),
+    "ldopf_server_destroy": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None

@@ -12,7 +12,9 @@
 #include <vector>
 
 #include "device.h"
+#include "host_util.h"
 #include "internal.h"
+#include "problem.h"
 
 namespace ldopf {
 
@@ -21,98 +23,7 @@ thread_local std::string g_detail;
 }
 
 void fail(int code, const std::string& detail) { throw Error{code, detail}; }
-
-static void hip_check(hipError_t e, const char* what) {
-    if (e == hipSuccess) return;
-    const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? LDOPF_OUT_OF_MEMORY : LDOPF_DEVICE_ERROR;
-    fail(code, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-// Owning device allocation.
-template <typename T>
-struct DevBuf {
-    T* p = nullptr;
-    size_t count = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        count = 0;
-    }
-    void alloc(size_t n, const char* what) {
-        release();
-        const size_t bytes = std::max<size_t>(1, n) * sizeof(T);
-        hip_check(hipMalloc(reinterpret_cast<void**>(&p), bytes), what);
-        count = n;
-    }
-    void upload(const std::vector<T>& v, hipStream_t s, const char* what) {
-        alloc(v.size(), what);
-        if (!v.empty()) hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), what);
-    }
-};
-
-}  // namespace ldopf
-
-using namespace ldopf;
-
-struct ldopf_problem {
-    ConsensusLP lp;
-    ldopf_options opts{};
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    bool fp32 = false;
-    Plan plan;
-    std::vector<int32_t> rank;
-    double precompute_ms = 0.0;
-    double last_sweep_ms = 0.0;
-    int64_t hist_len = 0;
-    bool have_x = false;
-    uint64_t spin_limit = 0;
-
-    DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart, prof;
-    double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double tick_ms = 1e-5;  // wall-clock tick in ms
-    DevBuf<int32_t> ns, ms, rank_d, flags;
-    DevBuf<int64_t> a_off, row_off, loc_off, basis_off;
-    DevBuf<PartInfo> parts;
-    DevBuf<SubMeta> subs;
-    DevBuf<int32_t> row_canon, var_gid, var_slot, var_slot_lo, var_slot_hi;
-    DevBuf<uint16_t> row_lvar, row_sub, var_copy_off, var_copy_rows, tk_sub;
-    DevBuf<uint8_t> var_writer;
-    DevBuf<unsigned char> bpart;
-    DevBuf<unsigned> bar;
-    DevBuf<SweepStatus> st;
-
-    ~ldopf_problem() {
-        if (stream) (void)hipStreamSynchronize(stream);
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
-    }
-};
-
-namespace {
-
-template <typename F>
-int guard(F&& f) {
-    try {
-        f();
-        return LDOPF_OK;
-    } catch (const Error& e) {
-        g_detail = e.detail;
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        g_detail = "host allocation failed";
-        return LDOPF_OUT_OF_MEMORY;
-    } catch (const std::exception& e) {
-        g_detail = e.what();
-        return LDOPF_DEVICE_ERROR;
-    }
-}
+void record_error_detail(const std::string& detail) { g_detail = detail; }
 
 void check_options(const ldopf_options& o) {
     if (!(o.rho > 0.0) || !std::isfinite(o.rho)) fail(LDOPF_INVALID_ARGUMENT, "rho must be positive and finite");
@@ -132,6 +43,12 @@ void check_options(const ldopf_options& o) {
     for (int r : o.reserved)
         if (r != 0) fail(LDOPF_INVALID_ARGUMENT, "reserved option fields must be zero");
 }
+
+}  // namespace ldopf
+
+using namespace ldopf;
+
+namespace {
 
 void init_state(ldopf_problem& h) {
     const ConsensusLP& lp = h.lp;
@@ -318,6 +235,7 @@ ldopf_problem* new_problem(const ldopf_options* opts, void* stream) {
         }
         hip_check(hipEventCreate(&h->ev0), "event");
         hip_check(hipEventCreate(&h->ev1), "event");
+        hip_check(hipEventCreateWithFlags(&h->done, hipEventDisableTiming), "event");
     } catch (...) {
         delete h;
         throw;
@@ -325,11 +243,108 @@ ldopf_problem* new_problem(const ldopf_options* opts, void* stream) {
     return h;
 }
 
-void need(const void* p, const char* what) {
-    if (!p) fail(LDOPF_INVALID_ARGUMENT, std::string(what) + " must not be NULL");
+}  // namespace
+
+namespace ldopf {
+
+ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipStream_t stream) {
+    ldopf_problem* h = new_problem(&opts, stream);
+    try {
+        h->lp = std::move(lp);
+        build_device(*h);
+    } catch (...) {
+        delete h;
+        throw;
+    }
+    return h;
 }
 
-}  // namespace
+void problem_launch(ldopf_problem& h) {
+    if (h.in_flight) fail(LDOPF_INVALID_ARGUMENT, "a solve is already in flight on this handle");
+    const int64_t want = h.opts.history ? std::min<int64_t>(std::max<int64_t>(h.opts.max_iter, 1), int64_t(1) << 22) : 1;
+    if (int64_t(h.hist.count) < want * 4) h.hist.alloc(size_t(want) * 4, "history");
+    hipError_t e;
+    hip_check(hipEventRecord(h.ev0, h.stream), "event");
+    if (h.fp32) {
+        e = launch_sweep(sweep_args<float>(h), h.plan.n_parts, h.plan.block_threads, size_t(h.plan.lds_bytes), h.stream);
+    } else {
+        e = launch_sweep(sweep_args<double>(h), h.plan.n_parts, h.plan.block_threads, size_t(h.plan.lds_bytes), h.stream);
+    }
+    hip_check(e, "sweep launch");
+    hip_check(hipEventRecord(h.ev1, h.stream), "event");
+    hip_check(hipMemcpyAsync(&h.last, h.st.p, sizeof(h.last), hipMemcpyDeviceToHost, h.stream), "download status");
+    hip_check(hipEventRecord(h.done, h.stream), "event");
+    h.in_flight = true;
+}
+
+bool problem_ready(const ldopf_problem& h) {
+    if (!h.in_flight) return true;
+    return hipEventQuery(h.done) == hipSuccess;
+}
+
+int problem_finish(ldopf_problem& h, ldopf_status* status) {
+    if (!h.in_flight) fail(LDOPF_INVALID_ARGUMENT, "no solve in flight on this handle");
+    h.in_flight = false;
+    hip_check(hipEventSynchronize(h.done), "sweep");
+    const SweepStatus st = h.last;
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, h.ev0, h.ev1), "event time");
+    h.last_sweep_ms = ms;
+    std::fill(h.phase_ms, h.phase_ms + 8, 0.0);
+    if (h.opts.profile) {
+        double ticks[8];
+        hip_check(hipMemcpy(ticks, h.prof.p, sizeof(ticks), hipMemcpyDeviceToHost), "download phase times");
+        for (int i = 0; i < 8; ++i) h.phase_ms[i] = ticks[i] * h.tick_ms;
+    }
+    h.hist_len = h.opts.history ? std::min<int64_t>(st.iters, int64_t(h.hist.count / 4)) : 0;
+    if (st.iters > 0) h.have_x = true;
+    if (st.flags & 1) fail(LDOPF_DEVICE_ERROR, "grid barrier wait timed out in the sweep kernel");
+    int code = LDOPF_OK;
+    if (st.flags & 2) {
+        code = LDOPF_NUMERICAL;
+        record_error_detail("non-finite residual sums");
+    } else if (h.opts.check_termination && !st.converged) {
+        code = LDOPF_NOT_CONVERGED;
+    }
+    if (status) {
+        status->iterations = st.iters;
+        status->converged = st.converged;
+        status->pres = st.pres;
+        status->dres = st.dres;
+        status->eps_prim = st.eps_p;
+        status->eps_dual = st.eps_d;
+        status->sweep_ms = ms;
+        status->precompute_ms = h.precompute_ms;
+        status->sweeps_computed = st.computed;
+        status->code = code;
+    }
+    return code;
+}
+
+int64_t problem_device_bytes(const ConsensusLP& lp, const ldopf_options& o) {
+    const int64_t S = lp.S, n = lp.n, nloc = int64_t(lp.gidx.size());
+    int64_t nn = 0;
+    for (int32_t v : lp.ns) nn += int64_t(v) * v;
+    const int64_t hist = o.history ? std::min<int64_t>(std::max<int64_t>(o.max_iter, 1), int64_t(1) << 22) * 32 : 32;
+    int64_t bytes = 8 * int64_t(lp.A.size() + lp.b.size()) + 8 * 2 * nn + 8 * nloc * 3 + 8 * n * 5 +
+                    S * (4 * 4 + 8 * 4 + 32) + nloc * (4 + 2 * 4 + 4 * 4 + 1) + 2 * 8 * nloc + 2 * 1024 * 64 +
+                    kBarWords * 4 + hist;
+    return bytes + 48 * 4096;  // allocation granularity of about 48 buffers
+}
+
+int32_t problem_parts_estimate(const ConsensusLP& lp, const ldopf_options& o) {
+    int dev = 0, cus = 256, lds = 163840;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+    }
+    std::vector<int32_t> rank(lp.S);
+    for (int64_t s = 0; s < lp.S; ++s) rank[s] = std::min(lp.ms[s], lp.ns[s]);
+    const Plan pl = make_plan(lp, rank, o.precision == LDOPF_FP32_MIXED, o.rows_per_part, o.block_threads, cus, lds);
+    return pl.n_parts;
+}
+
+}  // namespace ldopf
 
 extern "C" {
 
@@ -502,51 +517,10 @@ int ldopf_solve(ldopf_problem* h, ldopf_status* status) {
     int code = LDOPF_OK;
     const int rc = guard([&] {
         need(h, "handle");
-        const int64_t want = h->opts.history ? std::min<int64_t>(std::max<int64_t>(h->opts.max_iter, 1), int64_t(1) << 22) : 1;
-        if (int64_t(h->hist.count) < want * 4) h->hist.alloc(size_t(want) * 4, "history");
-        hipError_t e;
-        hip_check(hipEventRecord(h->ev0, h->stream), "event");
-        if (h->fp32) {
-            e = launch_sweep(sweep_args<float>(*h), h->plan.n_parts, h->plan.block_threads, size_t(h->plan.lds_bytes), h->stream);
-        } else {
-            e = launch_sweep(sweep_args<double>(*h), h->plan.n_parts, h->plan.block_threads, size_t(h->plan.lds_bytes), h->stream);
-        }
-        hip_check(e, "sweep launch");
-        hip_check(hipEventRecord(h->ev1, h->stream), "event");
-        SweepStatus st{};
-        hip_check(hipMemcpyAsync(&st, h->st.p, sizeof(st), hipMemcpyDeviceToHost, h->stream), "download status");
-        hip_check(hipStreamSynchronize(h->stream), "sweep");
-        float ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1), "event time");
-        h->last_sweep_ms = ms;
-        std::fill(h->phase_ms, h->phase_ms + 8, 0.0);
-        if (h->opts.profile) {
-            double ticks[8];
-            hip_check(hipMemcpy(ticks, h->prof.p, sizeof(ticks), hipMemcpyDeviceToHost), "download phase times");
-            for (int i = 0; i < 8; ++i) h->phase_ms[i] = ticks[i] * h->tick_ms;
-        }
-        h->hist_len = h->opts.history ? std::min<int64_t>(st.iters, int64_t(h->hist.count / 4)) : 0;
-        if (st.iters > 0) h->have_x = true;
-        if (st.flags & 1) fail(LDOPF_DEVICE_ERROR, "grid barrier wait timed out in the sweep kernel");
-        if (status) {
-            status->iterations = st.iters;
-            status->converged = st.converged;
-            status->pres = st.pres;
-            status->dres = st.dres;
-            status->eps_prim = st.eps_p;
-            status->eps_dual = st.eps_d;
-            status->sweep_ms = ms;
-            status->precompute_ms = h->precompute_ms;
-            status->sweeps_computed = st.computed;
-        }
-        if (st.flags & 2) {
-            code = LDOPF_NUMERICAL;
-            g_detail = "non-finite residual sums";
-        } else if (h->opts.check_termination && !st.converged) {
-            code = LDOPF_NOT_CONVERGED;
-        }
+        problem_launch(*h);
+        code = problem_finish(*h, status);
     });
-    if (status) status->code = rc != LDOPF_OK ? rc : code;
+    if (rc != LDOPF_OK && status) status->code = rc;
     return rc != LDOPF_OK ? rc : code;
 }
 

@@ -171,6 +171,8 @@ void m_entry(const double* r9, const double* x9, int phi, int psi, double& mp, d
 struct Row {
     std::vector<std::pair<int64_t, double>> a;
     double rhs = 0.0;
+    int32_t load = -1;    // load whose reference power this row carries
+    int64_t wglob = -1;   // global index of the load-scaled w coefficient
     void add(int64_t col, double v) { a.emplace_back(col, v); }
 };
 
@@ -238,9 +240,13 @@ struct Builder {
                 rp.add(L.load(l, f, PD), 1.0);
                 rp.add(L.w(i, f), -0.5 * a[f] * al);
                 rp.rhs = a[f] - 0.5 * a[f] * al;
+                rp.load = l;
+                rp.wglob = L.w(i, f);
                 rq.add(L.load(l, f, QD), 1.0);
                 rq.add(L.w(i, f), -0.5 * b[f] * be);
                 rq.rhs = b[f] - 0.5 * b[f] * be;
+                rq.load = l;
+                rq.wglob = L.w(i, f);
                 ep.add(L.load(l, f, PB), 1.0);
                 ep.add(L.load(l, f, PD), -1.0);
                 eq.add(L.load(l, f, QB), 1.0);
@@ -258,6 +264,8 @@ struct Builder {
             r.add(L.load(l, f, PD), 1.0);
             r.add(L.w(i, f), -1.5 * a[f] * V.alpha(l, f));
             r.rhs = a[f] - 0.5 * a[f] * V.alpha(l, f);
+            r.load = l;
+            r.wglob = L.w(i, f);
             rows.push_back(std::move(r));
         }
         for (int f = 0; f < 3; ++f) {
@@ -265,6 +273,8 @@ struct Builder {
             r.add(L.load(l, f, QD), 1.0);
             r.add(L.w(i, f), -1.5 * b[f] * V.beta(l, f));
             r.rhs = b[f] - 0.5 * b[f] * V.beta(l, f);
+            r.load = l;
+            r.wglob = L.w(i, f);
             rows.push_back(std::move(r));
         }
         Row sp, sq;
@@ -349,6 +359,11 @@ struct Builder {
                 lp.A[a0 + r * n + (it - vars.begin())] += v;
             }
             lp.b.push_back(rows[r].rhs);
+            lp.row_load.push_back(rows[r].load);
+            int32_t wc = -1;
+            if (rows[r].wglob >= 0)
+                wc = int32_t(std::lower_bound(vars.begin(), vars.end(), rows[r].wglob) - vars.begin());
+            lp.row_wcol.push_back(wc);
         }
         lp.gidx.insert(lp.gidx.end(), vars.begin(), vars.end());
         lp.ns.push_back(int32_t(n));
@@ -366,6 +381,7 @@ ConsensusLP assemble_network(const ldopf_network& net) {
     Layout L = make_layout(net);
     ConsensusLP lp;
     lp.n = L.n;
+    lp.n_load = net.n_load;
     lp.c.assign(L.n, 0.0);
     lp.lo.assign(L.n, -INFINITY);
     lp.hi.assign(L.n, INFINITY);

@@ -1,0 +1,1093 @@
+// Batched scenarios: one network, B load scenarios, solved together.
+//
+// Scenario k multiplies the reference powers of every load l by f[k][l].
+// That scales the right-hand side of the load's model rows and, for a
+// voltage-dependent load (alpha or beta > 0), also the squared-voltage
+// coefficient of those rows (Section II-A, VDLM-1 and VDLM-2). So:
+//   * a subsystem with no voltage-dependent load has one operator Abar_s for
+//     all scenarios; its local update for B scenarios is Y = Bbar - Abar_s V
+//     with V of size n_s x B, a small GEMM, run on MFMA
+//     (v_mfma_f32_16x16x4f32, 64-scenario tiles);
+//   * a subsystem with one has a different operator per scenario; its update
+//     runs in rank form per scenario (vector code, scenario-contiguous data).
+// bbar differs per scenario everywhere. Operators are precomputed in FP64 on
+// the device for every (subsystem, scenario) pair and stored in FP32; the
+// sweep (global update, local update, dual update) runs in FP32; residual
+// sums, the termination test and the per-scenario masks in FP64. Each
+// scenario stops at its own first sweep that passes the test (Section III-C)
+// and keeps that state while the others continue. C sweeps are captured in
+// one HIP graph; the host replays it until every scenario has stopped.
+//
+// State layout in HBM: row-major [copy or variable][scenario], scenarios
+// padded to Bp (a multiple of 64), so a wave reads 64 consecutive scenarios.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "gs_core.h"
+#include "host_util.h"
+#include "internal.h"
+
+namespace ldopf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kTile = 64;        // scenarios per wave
+constexpr int kZS = kTile + 1;   // padded LDS row stride of the MFMA kernel
+
+struct PrecomputeBatchArgs {
+    int64_t S, nloc, words;
+    int32_t k0, C, n_load;
+    const int32_t* ns;
+    const int32_t* ms;
+    const int64_t* a_off;
+    const int64_t* row_off;
+    const int64_t* loc_off;
+    const int64_t* basis_off;
+    const double* A;
+    const double* b;
+    const int32_t* row_load;
+    const int32_t* row_wcol;
+    const double* scale;  // [B][n_load]
+    double* tmp_basis;    // [C][words]
+    double* tmp_bbar;     // [C][nloc]
+    int32_t* tmp_rank;    // [C][S]
+    int32_t* tmp_bad;     // [C][S]
+    double tol_dep, tol_rhs;
+};
+
+struct PackArgs {
+    int64_t S, nloc, words;
+    int32_t k0, C, Bp;
+    const int32_t* ns;
+    const int64_t* loc_off;
+    const int64_t* basis_off;
+    const int32_t* rank;      // rank at unit scale
+    const int32_t* cls;       // 0 MFMA, 1 vector
+    const int32_t* vK;
+    const int32_t* vbrow;
+    const int64_t* wofs;      // first W row (units of Bp) of a vector-class subsystem
+    const double* tmp_basis;
+    const double* tmp_bbar;
+    const int32_t* tmp_rank;
+    const int32_t* tmp_bad;
+    float* BB;
+    float* W;
+    int32_t* flag;            // bit 1: rank changed with the scale, bit 2: inconsistent rows
+};
+
+struct BatchArgs {
+    int32_t B, Bp;
+    int64_t n, nloc;
+    const int32_t* ns;
+    const int64_t* loc_off;
+    const int32_t* gidx;
+    const int32_t* var_off;
+    const int32_t* var_copy;
+    const float* crho;
+    const float* lo;
+    const float* hi;
+    const float* invN;
+    float* X;
+    float* XS;
+    float* LAM;
+    const float* BB;
+    // MFMA class
+    int32_t n_mf_chunks;
+    const int32_t* mf_sub;
+    const int32_t* mf_chunk_off;
+    const float* ash;
+    const int64_t* ash_off;
+    // vector class
+    int32_t n_vec_chunks;
+    const int32_t* vec_sub;
+    const int32_t* vec_chunk_off;
+    const float* W;
+    const int64_t* wofs;  // indexed by subsystem
+    const int32_t* vK;
+    const int32_t* vmode;
+    // residuals and control
+    double* part;      // [part_rows][5][Bp]
+    int32_t mf_rows, part_rows;
+    int32_t* active;   // [Bp]
+    int32_t* conv;     // [Bp]
+    int64_t* iters;    // [Bp]
+    double* res;       // [Bp][4]
+    int32_t* sflags;   // [Bp]
+    int64_t* ctrl;     // [0] sweeps done, [1] all done, [2] active count, [3] arrivals
+    int64_t max_iter;
+    int32_t check;
+    double rho, eps_rel, eps_abs;
+};
+
+__global__ __launch_bounds__(256) void precompute_batch_kernel(PrecomputeBatchArgs a) {
+    __shared__ double sbeta[4][256];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t v = int64_t(blockIdx.x) * 4 + wv;
+    if (v >= a.S * a.C) return;
+    const int64_t s = v % a.S;
+    const int64_t kc = v / a.S;
+    const int64_t k = a.k0 + kc;
+    const double* fs = a.n_load > 0 ? a.scale + k * a.n_load : nullptr;
+    int bad = 0;
+    const int r = gs_project(lane, a.ns[s], a.ms[s], a.A + a.a_off[s], a.b + a.row_off[s], a.row_load + a.row_off[s],
+                             a.row_wcol + a.row_off[s], fs, a.tol_dep, a.tol_rhs,
+                             a.tmp_basis + kc * a.words + a.basis_off[s], sbeta[wv],
+                             a.tmp_bbar + kc * a.nloc + a.loc_off[s], nullptr, &bad);
+    if (lane == 0) {
+        a.tmp_rank[kc * a.S + s] = r;
+        a.tmp_bad[kc * a.S + s] = bad;
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_pack_kernel(PackArgs a) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t v = int64_t(blockIdx.x) * 4 + wv;
+    if (v >= a.S * a.C) return;
+    const int64_t s = v % a.S;
+    const int64_t kc = v / a.S;
+    const int64_t k = a.k0 + kc;
+    const int n = a.ns[s];
+    if (lane == 0) {
+        if (a.tmp_rank[kc * a.S + s] != a.rank[s]) atomicOr(a.flag, 1);
+        if (a.tmp_bad[kc * a.S + s]) atomicOr(a.flag, 2);
+    }
+    const double* bb = a.tmp_bbar + kc * a.nloc + a.loc_off[s];
+    for (int j = lane; j < n; j += 64) a.BB[(a.loc_off[s] + j) * a.Bp + k] = float(bb[j]);
+    if (a.cls[s] == 1) {
+        const int K = a.vK[s], brow = a.vbrow[s];
+        const double* U = a.tmp_basis + kc * a.words + a.basis_off[s];
+        for (int idx = lane; idx < K * n; idx += 64) {
+            const int kk = idx / n, jj = idx - kk * n;
+            a.W[(a.wofs[s] + idx) * a.Bp + k] = float(U[int64_t(brow + kk) * n + jj]);
+        }
+    }
+}
+
+// Global update (closed_1), one thread per (variable, scenario).
+__global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
+    if (a.ctrl[1]) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t v = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int sc = blockIdx.y * kTile + lane;
+    if (v >= a.n || !a.active[sc]) return;
+    const float irho = float(1.0 / a.rho);
+    float s = 0.f;
+    for (int q = a.var_off[v]; q < a.var_off[v + 1]; ++q) {
+        const int64_t c = a.var_copy[q];
+        s += a.XS[c * a.Bp + sc] - a.LAM[c * a.Bp + sc] * irho;
+    }
+    float x = (s - a.crho[v]) * a.invN[v];
+    x = x < a.lo[v] ? a.lo[v] : x;
+    x = x > a.hi[v] ? a.hi[v] : x;
+    a.X[v * a.Bp + sc] = x;
+}
+
+// Local + dual update of the MFMA class: Y = Bbar - Abar_s V per 64-scenario
+// tile; rows of Abar_s in 16-row tiles, scenarios in four 16-column tiles.
+// Operand layout of v_mfma_f32_16x16x4f32: lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16] and D[4 (l / 16) + i][l % 16], i < 4.
+__global__ __launch_bounds__(64) void batch_local_mfma_kernel(BatchArgs a) {
+    if (a.ctrl[1]) return;
+    extern __shared__ __align__(16) float sm[];
+    float* zs = sm;              // [n][kZS]
+    float* ls = sm + 64 * kZS;   // [n][kZS]
+    double* red = reinterpret_cast<double*>(sm + 2 * 64 * kZS);  // [4][64][5]
+    const int lane = threadIdx.x;
+    const int tile = blockIdx.y;
+    const int sc = tile * kTile + lane;
+    const float rho = float(a.rho), irho = float(1.0 / a.rho);
+    double p[4][5];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) p[nt][q] = 0.0;
+    for (int c = blockIdx.x; c < a.n_mf_chunks; c += gridDim.x) {
+        for (int q = a.mf_chunk_off[c]; q < a.mf_chunk_off[c + 1]; ++q) {
+            const int s = a.mf_sub[q];
+            const int n = a.ns[s];
+            const int64_t row0 = a.loc_off[s];
+            const float* Ab = a.ash + a.ash_off[q];
+            for (int j = 0; j < n; ++j) {
+                zs[j * kZS + lane] = a.X[int64_t(a.gidx[row0 + j]) * a.Bp + sc];
+                ls[j * kZS + lane] = a.LAM[(row0 + j) * a.Bp + sc];
+            }
+            __syncthreads();
+            for (int mt = 0; mt * 16 < n; ++mt) {
+                floatx4 acc[4];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                const int ar = mt * 16 + (lane & 15);
+                for (int kk = 0; kk * 4 < n; ++kk) {
+                    const int kc = kk * 4 + (lane >> 4);
+                    const float av = (ar < n && kc < n) ? Ab[ar * n + kc] : 0.f;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int bc = nt * 16 + (lane & 15);
+                        const float bv = kc < n ? zs[kc * kZS + bc] + ls[kc * kZS + bc] * irho : 0.f;
+                        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[nt], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int scl = nt * 16 + (lane & 15);
+                    const int scg = tile * kTile + scl;
+                    const bool on = a.active[scg] != 0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = mt * 16 + 4 * (lane >> 4) + i;
+                        if (row < n) {
+                            const int64_t cr = (row0 + row) * a.Bp + scg;
+                            const float y = a.BB[cr] - acc[nt][i];
+                            const float z = zs[row * kZS + scl];
+                            const float l0 = ls[row * kZS + scl];
+                            const float l1 = l0 + rho * (z - y);
+                            const float xo = a.XS[cr];
+                            if (on) {
+                                a.XS[cr] = y;
+                                a.LAM[cr] = l1;
+                                const double dz = double(z) - double(y), dx = double(y) - double(xo);
+                                p[nt][0] += dz * dz;
+                                p[nt][1] += dx * dx;
+                                p[nt][2] += double(z) * double(z);
+                                p[nt][3] += double(y) * double(y);
+                                p[nt][4] += double(l1) * double(l1);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // lanes l, l + 16, l + 32, l + 48 hold partial sums of the same scenarios
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) red[((lane >> 4) * 64 + nt * 16 + (lane & 15)) * 5 + q] = p[nt][q];
+    __syncthreads();
+    double* out = a.part + int64_t(blockIdx.x) * 5 * a.Bp;
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+        out[q * a.Bp + sc] = ((red[(0 * 64 + lane) * 5 + q] + red[(1 * 64 + lane) * 5 + q]) +
+                              red[(2 * 64 + lane) * 5 + q]) + red[(3 * 64 + lane) * 5 + q];
+}
+
+// Local + dual update of the vector class: per scenario, rank form
+// y = bbar + v - W'(W v) (mode 1) or bbar + W'(W v) (mode 0) with this
+// scenario's W. One lane per scenario.
+__global__ __launch_bounds__(64) void batch_local_vec_kernel(BatchArgs a, int nmax) {
+    if (a.ctrl[1]) return;
+    extern __shared__ __align__(16) float sm[];
+    float* zs = sm;               // [nmax][64]
+    float* ls = sm + nmax * 64;   // [nmax][64]
+    float* ts = sm + 2 * nmax * 64;  // [nmax][64]
+    const int lane = threadIdx.x;
+    const int sc = blockIdx.y * kTile + lane;
+    const bool on = a.active[sc] != 0;
+    const float rho = float(a.rho), irho = float(1.0 / a.rho);
+    double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;
+    for (int c = blockIdx.x; c < a.n_vec_chunks; c += gridDim.x) {
+        for (int q = a.vec_chunk_off[c]; q < a.vec_chunk_off[c + 1]; ++q) {
+            const int s = a.vec_sub[q];
+            const int n = a.ns[s], K = a.vK[s], mode = a.vmode[s];
+            const int64_t row0 = a.loc_off[s];
+            const float* W = a.W + a.wofs[s] * a.Bp + sc;
+            for (int j = 0; j < n; ++j) {
+                zs[j * 64 + lane] = a.X[int64_t(a.gidx[row0 + j]) * a.Bp + sc];
+                ls[j * 64 + lane] = a.LAM[(row0 + j) * a.Bp + sc];
+            }
+            for (int k = 0; k < K; ++k) {
+                float t = 0.f;
+                for (int j = 0; j < n; ++j) t += W[int64_t(k * n + j) * a.Bp] * (zs[j * 64 + lane] + ls[j * 64 + lane] * irho);
+                ts[k * 64 + lane] = t;
+            }
+            for (int j = 0; j < n; ++j) {
+                float acc = 0.f;
+                for (int k = 0; k < K; ++k) acc += W[int64_t(k * n + j) * a.Bp] * ts[k * 64 + lane];
+                const float z = zs[j * 64 + lane], l0 = ls[j * 64 + lane];
+                const float vj = z + l0 * irho;
+                const int64_t cr = (row0 + j) * a.Bp + sc;
+                const float y = mode ? a.BB[cr] + (vj - acc) : a.BB[cr] + acc;
+                const float l1 = l0 + rho * (z - y);
+                const float xo = a.XS[cr];
+                if (on) {
+                    a.XS[cr] = y;
+                    a.LAM[cr] = l1;
+                    const double dz = double(z) - double(y), dx = double(y) - double(xo);
+                    p0 += dz * dz;
+                    p1 += dx * dx;
+                    p2 += double(z) * double(z);
+                    p3 += double(y) * double(y);
+                    p4 += double(l1) * double(l1);
+                }
+            }
+        }
+    }
+    double* out = a.part + int64_t(a.mf_rows + blockIdx.x) * 5 * a.Bp;
+    out[0 * a.Bp + sc] = p0;
+    out[1 * a.Bp + sc] = p1;
+    out[2 * a.Bp + sc] = p2;
+    out[3 * a.Bp + sc] = p3;
+    out[4 * a.Bp + sc] = p4;
+}
+
+// Residual sums per scenario (fixed order: rows split over 4 waves, then the
+// waves in order), the termination test, the masks; the last block to finish
+// advances the sweep counter and decides whether the batch is done.
+__global__ __launch_bounds__(256) void batch_reduce_kernel(BatchArgs a) {
+    if (a.ctrl[1]) return;
+    __shared__ double red[4][5][64];
+    __shared__ int last;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int sc = blockIdx.x * kTile + lane;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int r = wv; r < a.part_rows; r += 4)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] += a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) red[wv][q][lane] = acc[q];
+    const int64_t t_now = a.ctrl[0] + 1;
+    __syncthreads();
+    if (wv == 0) {
+        double d[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) d[q] = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
+        int still = 0;
+        if (sc < a.B && a.active[sc]) {
+            const double sq = sqrt(double(a.nloc));
+            const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
+            const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
+            const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
+            a.iters[sc] = t_now;
+            a.res[sc * 4 + 0] = pres;
+            a.res[sc * 4 + 1] = dres;
+            a.res[sc * 4 + 2] = eps_p;
+            a.res[sc * 4 + 3] = eps_d;
+            const bool conv = pres <= eps_p && dres <= eps_d;
+            a.conv[sc] = conv;
+            const bool bad = !isfinite(d[0] + d[1] + d[2] + d[3] + d[4]);
+            if (bad) a.sflags[sc] |= 2;
+            still = !(bad || (a.check && conv));
+            if (!still) a.active[sc] = 0;
+        }
+        const unsigned long long ball = __ballot(still);
+        if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), (unsigned long long)__popcll(ball));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long prev = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[3]), 1ull);
+        last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const long long left = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), 0ull);
+        a.ctrl[0] = t_now;
+        a.ctrl[2] = 0;
+        a.ctrl[3] = 0;
+        a.ctrl[1] = (left == 0 || t_now >= a.max_iter) ? 1 : 0;
+    }
+}
+
+__global__ void batch_init_kernel(BatchArgs a, const double* x_init) {
+    // initial point of Section V-A for every scenario; plain stores
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t total = a.nloc * a.Bp;
+    if (i < total) {
+        const int64_t c = i / a.Bp;
+        a.XS[i] = float(x_init[a.gidx[c]]);
+        a.LAM[i] = 0.f;
+    }
+    if (i < a.n * a.Bp) a.X[i] = 0.f;
+    if (i < a.Bp) {
+        const int sc = int(i);
+        a.active[sc] = sc < a.B ? 1 : 0;
+        a.conv[sc] = 0;
+        a.iters[sc] = 0;
+        a.sflags[sc] = 0;
+        for (int q = 0; q < 4; ++q) a.res[sc * 4 + q] = 0.0;
+    }
+    if (i < 4) a.ctrl[i] = 0;
+}
+
+}  // namespace
+
+}  // namespace ldopf
+
+using namespace ldopf;
+
+struct ldopf_batch {
+    ConsensusLP lp;
+    ldopf_options opts{};
+    int32_t B = 0, Bp = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t graph_sweeps = 16;
+    int32_t mf_grid = 0, vec_grid = 0, nmax_vec = 0;
+    double precompute_ms = 0.0;
+    int64_t n_mf = 0, n_vec = 0;
+    std::vector<int32_t> mf_chunk_off_h, vec_chunk_off_h;
+    std::vector<int32_t> mf_h, vec_h;  // class lists (canonical subsystem ids)
+    int32_t rows_per_chunk = 0;
+
+    DevBuf<int32_t> ns, gidx, var_off, var_copy, mf_sub, mf_chunk_off, vec_sub, vec_chunk_off, vK, vmode;
+    DevBuf<int64_t> loc_off, ash_off, wofs, iters, ctrl;
+    DevBuf<float> crho, lo, hi, invN, X, XS, LAM, BB, ash, W;
+    DevBuf<double> x_init, part, res;
+    DevBuf<int32_t> active, conv, sflags;
+
+    ~ldopf_batch() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+BatchArgs batch_args(ldopf_batch& h) {
+    BatchArgs a{};
+    a.B = h.B;
+    a.Bp = h.Bp;
+    a.n = h.lp.n;
+    a.nloc = int64_t(h.lp.gidx.size());
+    a.ns = h.ns.p;
+    a.loc_off = h.loc_off.p;
+    a.gidx = h.gidx.p;
+    a.var_off = h.var_off.p;
+    a.var_copy = h.var_copy.p;
+    a.crho = h.crho.p;
+    a.lo = h.lo.p;
+    a.hi = h.hi.p;
+    a.invN = h.invN.p;
+    a.X = h.X.p;
+    a.XS = h.XS.p;
+    a.LAM = h.LAM.p;
+    a.BB = h.BB.p;
+    a.n_mf_chunks = int32_t(h.mf_chunk_off_h.size()) - 1;
+    a.mf_sub = h.mf_sub.p;
+    a.mf_chunk_off = h.mf_chunk_off.p;
+    a.ash = h.ash.p;
+    a.ash_off = h.ash_off.p;
+    a.n_vec_chunks = int32_t(h.vec_chunk_off_h.size()) - 1;
+    a.vec_sub = h.vec_sub.p;
+    a.vec_chunk_off = h.vec_chunk_off.p;
+    a.W = h.W.p;
+    a.wofs = h.wofs.p;
+    a.vK = h.vK.p;
+    a.vmode = h.vmode.p;
+    a.part = h.part.p;
+    a.mf_rows = h.mf_grid;
+    a.part_rows = h.mf_grid + h.vec_grid;
+    a.active = h.active.p;
+    a.conv = h.conv.p;
+    a.iters = h.iters.p;
+    a.res = h.res.p;
+    a.sflags = h.sflags.p;
+    a.ctrl = h.ctrl.p;
+    a.max_iter = h.opts.max_iter;
+    a.check = h.opts.check_termination;
+    a.rho = h.opts.rho;
+    a.eps_rel = h.opts.eps_rel;
+    a.eps_abs = h.opts.eps_abs;
+    return a;
+}
+
+size_t mfma_lds() { return size_t(2 * 64 * kZS) * 4 + size_t(4 * 64 * 5) * 8; }
+
+void enqueue_sweep(ldopf_batch& h, const BatchArgs& a) {
+    const int tiles = h.Bp / kTile;
+    hipLaunchKernelGGL(batch_global_kernel, dim3(unsigned((a.n + 3) / 4), tiles), dim3(256), 0, h.stream, a);
+    if (h.mf_grid > 0)
+        hipLaunchKernelGGL(batch_local_mfma_kernel, dim3(h.mf_grid, tiles), dim3(64), mfma_lds(), h.stream, a);
+    if (h.vec_grid > 0)
+        hipLaunchKernelGGL(batch_local_vec_kernel, dim3(h.vec_grid, tiles), dim3(64), size_t(3 * h.nmax_vec * 64) * 4,
+                           h.stream, a, h.nmax_vec);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(tiles), dim3(256), 0, h.stream, a);
+}
+
+// Chunks of a class list: consecutive subsystems up to rows_per_chunk copies.
+std::vector<int32_t> make_chunks(const std::vector<int32_t>& subs, const ConsensusLP& lp, int32_t rows_per_chunk) {
+    std::vector<int32_t> off{0};
+    int64_t rows = 0;
+    for (size_t q = 0; q < subs.size(); ++q) {
+        rows += lp.ns[subs[q]];
+        if (rows >= rows_per_chunk) {
+            off.push_back(int32_t(q + 1));
+            rows = 0;
+        }
+    }
+    if (off.back() != int32_t(subs.size())) off.push_back(int32_t(subs.size()));
+    return off;
+}
+
+void set_chunks(ldopf_batch& h, const std::vector<int32_t>& mf, const std::vector<int32_t>& vec, int32_t rows_per_chunk,
+                int32_t waves_per_tile) {
+    h.rows_per_chunk = rows_per_chunk;
+    h.mf_chunk_off_h = make_chunks(mf, h.lp, rows_per_chunk);
+    h.vec_chunk_off_h = make_chunks(vec, h.lp, rows_per_chunk);
+    const int32_t nmf = int32_t(h.mf_chunk_off_h.size()) - 1, nvec = int32_t(h.vec_chunk_off_h.size()) - 1;
+    h.mf_grid = std::min(nmf, waves_per_tile);
+    h.vec_grid = std::min(nvec, waves_per_tile);
+    h.mf_chunk_off.upload(h.mf_chunk_off_h, h.stream, "upload chunks");
+    h.vec_chunk_off.upload(h.vec_chunk_off_h, h.stream, "upload chunks");
+    h.part.alloc(size_t(std::max(1, h.mf_grid + h.vec_grid)) * 5 * h.Bp, "residual partials");
+    if (h.exec) {
+        (void)hipGraphExecDestroy(h.exec);
+        h.exec = nullptr;
+    }
+    if (h.graph) {
+        (void)hipGraphDestroy(h.graph);
+        h.graph = nullptr;
+    }
+}
+
+void build_graph(ldopf_batch& h) {
+    if (h.exec) return;
+    const BatchArgs a = batch_args(h);
+    hip_check(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal), "graph capture");
+    for (int i = 0; i < h.graph_sweeps; ++i) enqueue_sweep(h, a);
+    hip_check(hipStreamEndCapture(h.stream, &h.graph), "graph capture");
+    hip_check(hipGraphInstantiate(&h.exec, h.graph, nullptr, nullptr, 0), "graph instantiate");
+}
+
+void batch_reset(ldopf_batch& h) {
+    const BatchArgs a = batch_args(h);
+    const int64_t total = std::max<int64_t>(int64_t(h.lp.gidx.size()), h.lp.n) * h.Bp;
+    hipLaunchKernelGGL(batch_init_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, h.stream, a, h.x_init.p);
+    hip_check(hipGetLastError(), "batch init");
+    hip_check(hipStreamSynchronize(h.stream), "batch init");
+}
+
+// Runs the graph until every scenario stopped (or max_iter); returns sweeps.
+int64_t run_to_done(ldopf_batch& h, double* ms_out) {
+    if (ms_out) *ms_out = 0.0;
+    if (h.opts.max_iter == 0) return 0;
+    build_graph(h);
+    int64_t ctrl[2] = {0, 0};
+    hip_check(hipEventRecord(h.ev0, h.stream), "event");
+    for (;;) {
+        hip_check(hipGraphLaunch(h.exec, h.stream), "graph launch");
+        hip_check(hipMemcpyAsync(ctrl, h.ctrl.p, sizeof(ctrl), hipMemcpyDeviceToHost, h.stream), "download control");
+        hip_check(hipStreamSynchronize(h.stream), "batch sweep");
+        if (ctrl[1]) break;
+    }
+    hip_check(hipEventRecord(h.ev1, h.stream), "event");
+    hip_check(hipEventSynchronize(h.ev1), "event");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, h.ev0, h.ev1), "event time");
+    if (ms_out) *ms_out = ms;
+    return ctrl[0];
+}
+
+std::string tune_key(const ldopf_batch& h) {
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    std::ostringstream k;
+    k << prop.gcnArchName << "/cu" << prop.multiProcessorCount << "/S" << h.lp.S << "/N" << h.lp.gidx.size() << "/mf"
+      << h.n_mf << "/vec" << h.n_vec << "/B" << h.B;
+    return k.str();
+}
+
+bool read_tune_cache(const std::string& path, const std::string& key, int32_t* rows, int32_t* waves) {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        int32_t r, w;
+        if (is >> k >> r >> w && k == key) {
+            *rows = r;
+            *waves = w;
+            return true;
+        }
+    }
+    return false;
+}
+
+void write_tune_cache(const std::string& path, const std::string& key, int32_t rows, int32_t waves) {
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << " " << rows << " " << waves << "\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* load_scale, const ldopf_options* opts,
+                       void* stream, ldopf_batch** out) {
+    return guard([&] {
+        need(net, "net");
+        need(out, "out");
+        *out = nullptr;
+        if (n_scen < 1 || n_scen > 1024) fail(LDOPF_INVALID_ARGUMENT, "n_scen must be in [1, 1024]");
+        ldopf_options o;
+        ldopf_default_options(&o);
+        if (opts) o = *opts;
+        check_options(o);
+        if (o.precision != LDOPF_FP32_MIXED)
+            fail(LDOPF_UNSUPPORTED, "batched scenarios run in the FP32-mixed form (FP32 sweep, FP64 precompute and residuals)");
+        ConsensusLP lp = assemble_network(*net);
+        const int32_t nl = lp.n_load;
+        std::vector<double> scale(size_t(n_scen) * std::max(nl, 1), 1.0);
+        if (nl > 0) {
+            need(load_scale, "load_scale");
+            for (size_t i = 0; i < size_t(n_scen) * nl; ++i) {
+                if (!std::isfinite(load_scale[i])) fail(LDOPF_INVALID_ARGUMENT, "non-finite load scale");
+                scale[i] = load_scale[i];
+            }
+        }
+        auto* h = new ldopf_batch();
+        try {
+            h->lp = std::move(lp);
+            h->opts = o;
+            h->B = n_scen;
+            h->Bp = (n_scen + kTile - 1) / kTile * kTile;
+            hip_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "stream");
+            hip_check(hipEventCreate(&h->ev0), "event");
+            hip_check(hipEventCreate(&h->ev1), "event");
+            if (stream) {
+                // order after the caller's pending work
+                hipEvent_t e;
+                hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+                hip_check(hipEventRecord(e, static_cast<hipStream_t>(stream)), "event");
+                hip_check(hipStreamWaitEvent(h->stream, e, 0), "event");
+                (void)hipEventDestroy(e);
+            }
+            ConsensusLP& L = h->lp;
+            hipStream_t s = h->stream;
+            const int64_t S = L.S, nloc = int64_t(L.gidx.size());
+            for (int32_t n : L.ns)
+                if (n > 255) fail(LDOPF_UNSUPPORTED, "subsystems with more than 255 variables are not supported on the device");
+            std::vector<int64_t> boff(S + 1, 0);
+            for (int64_t i = 0; i < S; ++i) boff[i + 1] = boff[i] + int64_t(L.ns[i]) * L.ns[i];
+            const int64_t words = boff[S];
+
+            // device inputs of the precompute
+            DevBuf<double> A, b, basis, abar, bbar, sc_d, tmp_basis, tmp_bbar;
+            DevBuf<int32_t> ms, rank_d, flags_d, row_load, row_wcol, tmp_rank, tmp_bad, cls_d, vbrow_d, flag_d;
+            DevBuf<int64_t> a_off, row_off, basis_off;
+            A.upload(L.A, s, "upload A");
+            b.upload(L.b, s, "upload b");
+            h->ns.upload(L.ns, s, "upload n_s");
+            ms.upload(L.ms, s, "upload m_s");
+            a_off.upload(L.a_off, s, "upload offsets");
+            row_off.upload(L.row_off, s, "upload offsets");
+            h->loc_off.upload(L.loc_off, s, "upload offsets");
+            basis_off.upload(boff, s, "upload offsets");
+            row_load.upload(L.row_load, s, "upload load rows");
+            row_wcol.upload(L.row_wcol, s, "upload load rows");
+            sc_d.upload(scale, s, "upload load scale");
+            basis.alloc(words, "basis");
+            abar.alloc(words, "abar");
+            bbar.alloc(nloc, "bbar");
+            rank_d.alloc(S, "rank");
+            flags_d.alloc(S, "flags");
+
+            hip_check(hipEventRecord(h->ev0, s), "event");
+            // unit-scale operators: ranks and the shared Abar of the MFMA class
+            PrecomputeArgs pa{};
+            pa.S = S;
+            pa.ns = h->ns.p;
+            pa.ms = ms.p;
+            pa.a_off = a_off.p;
+            pa.row_off = row_off.p;
+            pa.loc_off = h->loc_off.p;
+            pa.basis_off = basis_off.p;
+            pa.A = A.p;
+            pa.b = b.p;
+            pa.basis = basis.p;
+            pa.abar = abar.p;
+            pa.bbar = bbar.p;
+            pa.rank = rank_d.p;
+            pa.flags = flags_d.p;
+            pa.tol_dep = 1e-10;
+            pa.tol_rhs = 1e-9;
+            hip_check(launch_precompute(pa, s), "precompute");
+            std::vector<int32_t> rank(S), flags(S);
+            hip_check(hipMemcpyAsync(rank.data(), rank_d.p, S * 4, hipMemcpyDeviceToHost, s), "download ranks");
+            hip_check(hipMemcpyAsync(flags.data(), flags_d.p, S * 4, hipMemcpyDeviceToHost, s), "download flags");
+            hip_check(hipStreamSynchronize(s), "precompute");
+            for (int64_t i = 0; i < S; ++i)
+                if (flags[i]) fail(LDOPF_INCONSISTENT_SUBSYSTEM, "subsystem " + std::to_string(i) + " is inconsistent");
+
+            // classes: shared operator (no load-scaled coefficient, n_s <= 64) -> MFMA
+            std::vector<int32_t> cls(S, 0), vK(S, 0), vbrow(S, 0), vmode(S, 0);
+            std::vector<int64_t> wofs(S, 0), ash_off_s(S, 0);
+            std::vector<int32_t> mf, vec;
+            int64_t wrows = 0, ash_words = 0;
+            int32_t nmax_vec = 1;
+            for (int64_t i = 0; i < S; ++i) {
+                bool scaled = false;
+                for (int64_t r = L.row_off[i]; r < L.row_off[i + 1]; ++r) {
+                    const int32_t wc = L.row_wcol[r];
+                    if (L.row_load[r] >= 0 && wc >= 0 &&
+                        L.A[L.a_off[i] + (r - L.row_off[i]) * L.ns[i] + wc] != 0.0)
+                        scaled = true;
+                }
+                const int32_t n = L.ns[i];
+                if (!scaled && n <= 64) {
+                    cls[i] = 0;
+                    ash_off_s[i] = ash_words;
+                    ash_words += int64_t(n) * n;
+                    mf.push_back(int32_t(i));
+                } else {
+                    cls[i] = 1;
+                    const int32_t r = rank[i];
+                    vmode[i] = r <= n - r ? 1 : 0;
+                    vK[i] = std::min(r, n - r);
+                    vbrow[i] = vmode[i] ? 0 : r;
+                    wofs[i] = wrows;
+                    wrows += int64_t(vK[i]) * n;
+                    nmax_vec = std::max(nmax_vec, n);
+                    vec.push_back(int32_t(i));
+                }
+            }
+            h->n_mf = int64_t(mf.size());
+            h->n_vec = int64_t(vec.size());
+            h->nmax_vec = nmax_vec;
+            {
+                const size_t vec_lds = size_t(3 * nmax_vec * 64) * 4;
+                if (vec_lds > 163840) fail(LDOPF_UNSUPPORTED, "a voltage-dependent subsystem is too large for the batched path");
+                if (vec_lds > 65536)
+                    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_local_vec_kernel),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(vec_lds)),
+                              "vector kernel LDS");
+            }
+            const int32_t Bp = h->Bp;
+            h->BB.alloc(size_t(nloc) * Bp, "scenario bbar");
+            h->W.alloc(size_t(std::max<int64_t>(wrows, 1)) * Bp, "scenario operators");
+            cls_d.upload(cls, s, "upload classes");
+            h->vK.upload(vK, s, "upload classes");
+            vbrow_d.upload(vbrow, s, "upload classes");
+            h->vmode.upload(vmode, s, "upload classes");
+            h->wofs.upload(wofs, s, "upload classes");
+            flag_d.alloc(1, "flag");
+            hip_check(hipMemsetAsync(flag_d.p, 0, 4, s), "flag");
+            // zero the padded scenario columns of BB and W
+            hip_check(hipMemsetAsync(h->BB.p, 0, h->BB.count * 4, s), "clear");
+            hip_check(hipMemsetAsync(h->W.p, 0, h->W.count * 4, s), "clear");
+
+            // per-scenario operators, in chunks of scenarios to bound the scratch
+            const int64_t budget = int64_t(512) << 20;
+            const int32_t C = int32_t(std::max<int64_t>(1, std::min<int64_t>(n_scen, budget / std::max<int64_t>(1, 8 * (words + nloc)))));
+            tmp_basis.alloc(size_t(C) * words, "scratch");
+            tmp_bbar.alloc(size_t(C) * nloc, "scratch");
+            tmp_rank.alloc(size_t(C) * S, "scratch");
+            tmp_bad.alloc(size_t(C) * S, "scratch");
+            for (int32_t k0 = 0; k0 < n_scen; k0 += C) {
+                const int32_t cn = std::min(C, n_scen - k0);
+                PrecomputeBatchArgs pb{};
+                pb.S = S;
+                pb.nloc = nloc;
+                pb.words = words;
+                pb.k0 = k0;
+                pb.C = cn;
+                pb.n_load = nl;
+                pb.ns = h->ns.p;
+                pb.ms = ms.p;
+                pb.a_off = a_off.p;
+                pb.row_off = row_off.p;
+                pb.loc_off = h->loc_off.p;
+                pb.basis_off = basis_off.p;
+                pb.A = A.p;
+                pb.b = b.p;
+                pb.row_load = row_load.p;
+                pb.row_wcol = row_wcol.p;
+                pb.scale = sc_d.p;
+                pb.tmp_basis = tmp_basis.p;
+                pb.tmp_bbar = tmp_bbar.p;
+                pb.tmp_rank = tmp_rank.p;
+                pb.tmp_bad = tmp_bad.p;
+                pb.tol_dep = 1e-10;
+                pb.tol_rhs = 1e-9;
+                const unsigned grid = unsigned((S * cn + 3) / 4);
+                hipLaunchKernelGGL(precompute_batch_kernel, dim3(grid), dim3(256), 0, s, pb);
+                hip_check(hipGetLastError(), "batched precompute");
+                PackArgs pk{};
+                pk.S = S;
+                pk.nloc = nloc;
+                pk.words = words;
+                pk.k0 = k0;
+                pk.C = cn;
+                pk.Bp = Bp;
+                pk.ns = h->ns.p;
+                pk.loc_off = h->loc_off.p;
+                pk.basis_off = basis_off.p;
+                pk.rank = rank_d.p;
+                pk.cls = cls_d.p;
+                pk.vK = h->vK.p;
+                pk.vbrow = vbrow_d.p;
+                pk.wofs = h->wofs.p;
+                pk.tmp_basis = tmp_basis.p;
+                pk.tmp_bbar = tmp_bbar.p;
+                pk.tmp_rank = tmp_rank.p;
+                pk.tmp_bad = tmp_bad.p;
+                pk.BB = h->BB.p;
+                pk.W = h->W.p;
+                pk.flag = flag_d.p;
+                hipLaunchKernelGGL(batch_pack_kernel, dim3(grid), dim3(256), 0, s, pk);
+                hip_check(hipGetLastError(), "batched pack");
+            }
+            hip_check(hipEventRecord(h->ev1, s), "event");
+            int32_t flag = 0;
+            hip_check(hipMemcpyAsync(&flag, flag_d.p, 4, hipMemcpyDeviceToHost, s), "download flag");
+            hip_check(hipStreamSynchronize(s), "batched precompute");
+            float pms = 0.f;
+            hip_check(hipEventElapsedTime(&pms, h->ev0, h->ev1), "event time");
+            h->precompute_ms = pms;
+            if (flag & 2) fail(LDOPF_INCONSISTENT_SUBSYSTEM, "a scaled subsystem has inconsistent rows");
+            if (flag & 1) fail(LDOPF_UNSUPPORTED, "a subsystem's rank changes with the load scale");
+
+            // shared FP32 operators of the MFMA class
+            std::vector<double> abar_h(words);
+            hip_check(hipMemcpy(abar_h.data(), abar.p, words * 8, hipMemcpyDeviceToHost), "download abar");
+            std::vector<float> ash(std::max<int64_t>(ash_words, 1));
+            std::vector<int64_t> ash_off;
+            for (int32_t i : mf) {
+                const int64_t nn = int64_t(L.ns[i]) * L.ns[i];
+                for (int64_t t = 0; t < nn; ++t) ash[ash_off_s[i] + t] = float(abar_h[boff[i] + t]);
+                ash_off.push_back(ash_off_s[i]);
+            }
+            h->ash.upload(ash, s, "upload shared operators");
+            h->ash_off.upload(ash_off.empty() ? std::vector<int64_t>{0} : ash_off, s, "upload shared operators");
+            h->mf_h = mf;
+            h->vec_h = vec;
+            h->mf_sub.upload(mf.empty() ? std::vector<int32_t>{0} : mf, s, "upload classes");
+            h->vec_sub.upload(vec.empty() ? std::vector<int32_t>{0} : vec, s, "upload classes");
+
+            // consensus structure: copies of each variable, global data in FP32
+            std::vector<int32_t> g32(nloc), var_off(L.n + 1, 0), var_copy(nloc);
+            for (int64_t c = 0; c < nloc; ++c) {
+                g32[c] = int32_t(L.gidx[c]);
+                var_off[L.gidx[c] + 1]++;
+            }
+            for (int64_t v = 0; v < L.n; ++v) var_off[v + 1] += var_off[v];
+            std::vector<int32_t> fill(var_off.begin(), var_off.end() - 1);
+            for (int64_t c = 0; c < nloc; ++c) var_copy[fill[L.gidx[c]]++] = int32_t(c);
+            std::vector<float> crho(L.n), lo(L.n), hi(L.n), invN(L.n);
+            for (int64_t v = 0; v < L.n; ++v) {
+                crho[v] = float(L.c[v] / o.rho);
+                lo[v] = float(L.lo[v]);
+                hi[v] = float(L.hi[v]);
+                invN[v] = float(1.0 / double(var_off[v + 1] - var_off[v]));
+            }
+            h->gidx.upload(g32, s, "upload gidx");
+            h->var_off.upload(var_off, s, "upload copies");
+            h->var_copy.upload(var_copy, s, "upload copies");
+            h->crho.upload(crho, s, "upload c");
+            h->lo.upload(lo, s, "upload lo");
+            h->hi.upload(hi, s, "upload hi");
+            h->invN.upload(invN, s, "upload counts");
+            h->x_init.upload(L.x_init, s, "upload start");
+            h->X.alloc(size_t(L.n) * Bp, "x");
+            h->XS.alloc(size_t(nloc) * Bp, "x_s");
+            h->LAM.alloc(size_t(nloc) * Bp, "lambda");
+            h->active.alloc(Bp, "masks");
+            h->conv.alloc(Bp, "masks");
+            h->sflags.alloc(Bp, "masks");
+            h->iters.alloc(Bp, "iterations");
+            h->res.alloc(size_t(Bp) * 4, "residuals");
+            h->ctrl.alloc(4, "control");
+            const int32_t rows = o.rows_per_part > 0 ? o.rows_per_part : 256;
+            set_chunks(*h, mf, vec, rows, 1024);
+            batch_reset(*h);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+int ldopf_batch_destroy(ldopf_batch* h) {
+    return guard([&] { delete h; });
+}
+
+int ldopf_batch_reset(ldopf_batch* h) {
+    return guard([&] {
+        need(h, "handle");
+        batch_reset(*h);
+    });
+}
+
+int ldopf_batch_solve(ldopf_batch* h, ldopf_batch_status* st) {
+    return guard([&] {
+        need(h, "handle");
+        double ms = 0.0;
+        const int64_t sweeps = run_to_done(*h, &ms);
+        if (st) {
+            std::memset(st, 0, sizeof(*st));
+            std::vector<int32_t> conv(h->Bp), fl(h->Bp);
+            hip_check(hipMemcpy(conv.data(), h->conv.p, h->Bp * 4, hipMemcpyDeviceToHost), "download masks");
+            hip_check(hipMemcpy(fl.data(), h->sflags.p, h->Bp * 4, hipMemcpyDeviceToHost), "download masks");
+            int32_t nc = 0, nbad = 0;
+            for (int i = 0; i < h->B; ++i) {
+                nc += conv[i] != 0;
+                nbad += (fl[i] & 2) != 0;
+            }
+            st->sweeps = sweeps;
+            st->n_scen = h->B;
+            st->n_converged = nc;
+            st->n_numerical = nbad;
+            st->solve_ms = ms;
+            st->precompute_ms = h->precompute_ms;
+            st->code = nbad ? LDOPF_NUMERICAL : (h->opts.check_termination && nc < h->B ? LDOPF_NOT_CONVERGED : LDOPF_OK);
+        }
+    });
+}
+
+int ldopf_batch_get_scenario(const ldopf_batch* h, int32_t scen, ldopf_status* st) {
+    return guard([&] {
+        need(h, "handle");
+        need(st, "status");
+        if (scen < 0 || scen >= h->B) fail(LDOPF_INVALID_ARGUMENT, "scenario out of range");
+        int64_t it = 0;
+        int32_t conv = 0, fl = 0;
+        double r[4];
+        hip_check(hipMemcpy(&it, h->iters.p + scen, 8, hipMemcpyDeviceToHost), "download");
+        hip_check(hipMemcpy(&conv, h->conv.p + scen, 4, hipMemcpyDeviceToHost), "download");
+        hip_check(hipMemcpy(&fl, h->sflags.p + scen, 4, hipMemcpyDeviceToHost), "download");
+        hip_check(hipMemcpy(r, h->res.p + 4 * int64_t(scen), 32, hipMemcpyDeviceToHost), "download");
+        std::memset(st, 0, sizeof(*st));
+        st->iterations = it;
+        st->sweeps_computed = it;
+        st->converged = conv;
+        st->pres = r[0];
+        st->dres = r[1];
+        st->eps_prim = r[2];
+        st->eps_dual = r[3];
+        st->precompute_ms = h->precompute_ms;
+        st->code = (fl & 2) ? LDOPF_NUMERICAL : (conv ? LDOPF_OK : LDOPF_NOT_CONVERGED);
+    });
+}
+
+int ldopf_batch_get_global(const ldopf_batch* h, int32_t scen, double* x, int64_t cap) {
+    return guard([&] {
+        need(h, "handle");
+        need(x, "x");
+        if (scen < 0 || scen >= h->B) fail(LDOPF_INVALID_ARGUMENT, "scenario out of range");
+        if (cap < h->lp.n) fail(LDOPF_BUFFER_TOO_SMALL, "x needs n entries");
+        std::vector<float> col(h->lp.n);
+        hip_check(hipMemcpy2D(col.data(), 4, h->X.p + scen, size_t(h->Bp) * 4, 4, h->lp.n, hipMemcpyDeviceToHost), "download x");
+        for (int64_t v = 0; v < h->lp.n; ++v) x[v] = col[v];
+    });
+}
+
+int ldopf_batch_get_local(const ldopf_batch* h, int32_t scen, double* xs, double* lam, int64_t cap) {
+    return guard([&] {
+        need(h, "handle");
+        if (scen < 0 || scen >= h->B) fail(LDOPF_INVALID_ARGUMENT, "scenario out of range");
+        const int64_t nl = int64_t(h->lp.gidx.size());
+        if (cap < nl) fail(LDOPF_BUFFER_TOO_SMALL, "x_s and lambda need N_loc entries");
+        std::vector<float> col(nl);
+        if (xs) {
+            hip_check(hipMemcpy2D(col.data(), 4, h->XS.p + scen, size_t(h->Bp) * 4, 4, nl, hipMemcpyDeviceToHost), "download x_s");
+            for (int64_t c = 0; c < nl; ++c) xs[c] = col[c];
+        }
+        if (lam) {
+            hip_check(hipMemcpy2D(col.data(), 4, h->LAM.p + scen, size_t(h->Bp) * 4, 4, nl, hipMemcpyDeviceToHost), "download lambda");
+            for (int64_t c = 0; c < nl; ++c) lam[c] = col[c];
+        }
+    });
+}
+
+int ldopf_batch_get_sizes(const ldopf_batch* h, ldopf_batch_sizes* o) {
+    return guard([&] {
+        need(h, "handle");
+        need(o, "out");
+        std::memset(o, 0, sizeof(*o));
+        o->n = h->lp.n;
+        o->n_sub = h->lp.S;
+        o->n_local = int64_t(h->lp.gidx.size());
+        o->n_scen = h->B;
+        o->n_scen_padded = h->Bp;
+        o->n_mfma_subsystems = h->n_mf;
+        o->n_vector_subsystems = h->n_vec;
+        o->scenario_operator_words = int64_t(h->W.count);
+        o->shared_operator_words = int64_t(h->ash.count);
+        o->rows_per_chunk = h->rows_per_chunk;
+        o->waves_per_tile = std::max(h->mf_grid, h->vec_grid);
+        o->graph_sweeps = h->graph_sweeps;
+    });
+}
+
+int ldopf_batch_tune(ldopf_batch* h, const char* cache_path, int32_t* rows_per_chunk, int32_t* waves_per_tile) {
+    return guard([&] {
+        need(h, "handle");
+        std::string path;
+        if (cache_path) path = cache_path;
+        const std::string key = tune_key(*h);
+        const std::vector<int32_t> mf = h->mf_h, vec = h->vec_h;
+        int32_t best_r = h->rows_per_chunk, best_w = std::max(h->mf_grid, h->vec_grid);
+        if (path.empty() || !read_tune_cache(path, key, &best_r, &best_w)) {
+            // time a short fixed number of sweeps for each candidate
+            const int64_t keep_iter = h->opts.max_iter;
+            const int32_t keep_check = h->opts.check_termination;
+            h->opts.max_iter = 2 * h->graph_sweeps;
+            h->opts.check_termination = 0;
+            double best = 1e300;
+            for (int32_t r : {64, 128, 256, 512})
+                for (int32_t w : {256, 1024, 4096}) {
+                    set_chunks(*h, mf, vec, r, w);
+                    batch_reset(*h);
+                    double ms = 0.0;
+                    run_to_done(*h, &ms);
+                    if (ms < best) {
+                        best = ms;
+                        best_r = r;
+                        best_w = w;
+                    }
+                }
+            h->opts.max_iter = keep_iter;
+            h->opts.check_termination = keep_check;
+            if (!path.empty()) write_tune_cache(path, key, best_r, best_w);
+        }
+        set_chunks(*h, mf, vec, best_r, best_w);
+        batch_reset(*h);
+        if (rows_per_chunk) *rows_per_chunk = best_r;
+        if (waves_per_tile) *waves_per_tile = best_w;
+    });
+}
+
+int ldopf_batch_set_options(ldopf_batch* h, const ldopf_options* opts) {
+    return guard([&] {
+        need(h, "handle");
+        need(opts, "opts");
+        check_options(*opts);
+        if (opts->precision != h->opts.precision) fail(LDOPF_INVALID_ARGUMENT, "precision is fixed at creation");
+        if (opts->rho != h->opts.rho) fail(LDOPF_INVALID_ARGUMENT, "rho is fixed at creation for a batch");
+        h->opts = *opts;
+        if (h->exec) {
+            (void)hipGraphExecDestroy(h->exec);
+            h->exec = nullptr;
+        }
+        if (h->graph) {
+            (void)hipGraphDestroy(h->graph);
+            h->graph = nullptr;
+        }
+    });
+}
+
+}  // extern "C"

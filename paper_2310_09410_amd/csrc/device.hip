@@ -33,16 +33,11 @@
 #include "internal.h"
 #include "layout.h"
 #include "device.h"
+#include "gs_core.h"
 
 namespace ldopf {
 
 namespace {
-
-__device__ inline double wave_sum(double v) {
-    // xor butterfly: every lane ends with the same bits (addition commutes)
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
 
 // DPP lane moves (gfx9 encodings): quad_perm [1,0,3,2] swaps neighbours,
 // quad_perm [2,3,0,1] swaps pairs, row_half_mirror reverses each group of 8,
@@ -116,140 +111,10 @@ __global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs a) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t s = int64_t(blockIdx.x) * 4 + wv;
     if (s >= a.S) return;
-    const int n = a.ns[s], m = a.ms[s];
-    const double* As = a.A + a.a_off[s];
-    const double* bs = a.b + a.row_off[s];
-    double* U = a.basis + a.basis_off[s];
-    double* beta = sbeta[wv];
-    double bmax = 0.0;
-    for (int i = 0; i < m; ++i) bmax = fmax(bmax, fabs(bs[i]));
-    int r = 0, bad = 0;
-    for (int i = 0; i < m; ++i) {
-        double ar[4];
-        double nn = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = lane + 64 * q;
-            ar[q] = c < n ? As[int64_t(i) * n + c] : 0.0;
-            nn += ar[q] * ar[q];
-        }
-        const double nrm0 = sqrt(wave_sum(nn));
-        double bi = bs[i];
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int k = 0; k < r; ++k) {
-                double d = 0.0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int c = lane + 64 * q;
-                    if (c < n) d += ar[q] * U[int64_t(k) * n + c];
-                }
-                d = wave_sum(d);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int c = lane + 64 * q;
-                    if (c < n) ar[q] -= d * U[int64_t(k) * n + c];
-                }
-                bi -= d * beta[k];
-            }
-        }
-        nn = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) nn += ar[q] * ar[q];
-        const double nr = sqrt(wave_sum(nn));
-        if (nrm0 > 0.0 && nr > a.tol_dep * nrm0 && r < n) {
-            const double inv = 1.0 / nr;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = lane + 64 * q;
-                if (c < n) U[int64_t(r) * n + c] = ar[q] * inv;
-            }
-            if (lane == 0) beta[r] = bi * inv;
-            ++r;
-        } else if (fabs(bi) > a.tol_rhs * (1.0 + bmax)) {
-            bad = 1;  // dependent row with an inconsistent right-hand side
-        }
-    }
-    // complete the basis: greedily take the unit vector farthest from the span
-    for (int q2 = r; q2 < n; ++q2) {
-        double best = -1.0;
-        int bidx = 0x7fffffff;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = lane + 64 * q;
-            if (c < n) {
-                double res = 1.0;
-                for (int k = 0; k < q2; ++k) {
-                    const double u = U[int64_t(k) * n + c];
-                    res -= u * u;
-                }
-                if (res > best) { best = res; bidx = c; }
-            }
-        }
-        for (int mm = 32; mm >= 1; mm >>= 1) {
-            const double ob = __shfl_xor(best, mm, 64);
-            const int oi = __shfl_xor(bidx, mm, 64);
-            if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
-        }
-        double ar[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ar[q] = (lane + 64 * q) == bidx ? 1.0 : 0.0;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int k = 0; k < q2; ++k) {
-                double d = 0.0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int c = lane + 64 * q;
-                    if (c < n) d += ar[q] * U[int64_t(k) * n + c];
-                }
-                d = wave_sum(d);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int c = lane + 64 * q;
-                    if (c < n) ar[q] -= d * U[int64_t(k) * n + c];
-                }
-            }
-        }
-        double nn = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) nn += ar[q] * ar[q];
-        const double inv = 1.0 / sqrt(wave_sum(nn));
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = lane + 64 * q;
-            if (c < n) U[int64_t(q2) * n + c] = ar[q] * inv;
-        }
-    }
-    // bbar = Q' beta over the row-space rows
-    double* bb = a.bbar + a.loc_off[s];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = lane + 64 * q;
-        if (c < n) {
-            double acc = 0.0;
-            for (int k = 0; k < r; ++k) acc += beta[k] * U[int64_t(k) * n + c];
-            bb[c] = acc;
-        }
-    }
-    // dense Abar = Q'Q - I; entry (i, c) needs column i, owned by lane i % 64
-    double* Ab = a.abar + a.basis_off[s];
-    for (int i = 0; i < n; ++i) {
-        const int owner = i & 63;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < r; ++k) {
-            const double mine = lane == owner ? U[int64_t(k) * n + i] : 0.0;
-            const double ui = __shfl(mine, owner, 64);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = lane + 64 * q;
-                if (c < n) acc[q] += ui * U[int64_t(k) * n + c];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = lane + 64 * q;
-            if (c < n) Ab[int64_t(i) * n + c] = acc[q] - (c == i ? 1.0 : 0.0);
-        }
-    }
+    int bad = 0;
+    const int r = gs_project(lane, a.ns[s], a.ms[s], a.A + a.a_off[s], a.b + a.row_off[s], nullptr, nullptr, nullptr,
+                             a.tol_dep, a.tol_rhs, a.basis + a.basis_off[s], sbeta[wv], a.bbar + a.loc_off[s],
+                             a.abar + a.basis_off[s], &bad);
     if (lane == 0) {
         a.rank[s] = r;
         a.flags[s] = bad;

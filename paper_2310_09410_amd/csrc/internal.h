@@ -30,6 +30,12 @@ struct ConsensusLP {
     std::vector<int64_t> loc_off, row_off, a_off;
     std::vector<double> A, b;
     std::vector<int64_t> gidx;
+    // Load scaling (network path only): for each row, the load whose
+    // reference powers it carries (-1: none) and the local column of its
+    // squared-voltage coefficient (-1: none). Scaling load l by f multiplies
+    // that row's right-hand side and that coefficient by f.
+    std::vector<int32_t> row_load, row_wcol;
+    int32_t n_load = 0;
     // Optional order in which subsystems sit next to each other in the network
     // (a depth-first walk of the feeder); used to cut the problem into
     // workgroup parts that share few variables. Empty: input order.

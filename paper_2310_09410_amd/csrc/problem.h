@@ -1,0 +1,78 @@
+// The problem handle of the plain solver and the internal calls the serving
+// runtime shares with the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "device.h"
+#include "host_util.h"
+#include "internal.h"
+
+// The C ABI names its handle at global scope; its members are library types.
+using ldopf::ConsensusLP;
+using ldopf::DevBuf;
+using ldopf::PartInfo;
+using ldopf::Plan;
+using ldopf::SubMeta;
+using ldopf::SweepStatus;
+
+struct ldopf_problem {
+    SweepStatus last{};  // status read back by the last finished solve
+    bool in_flight = false;
+    ConsensusLP lp;
+    ldopf_options opts{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
+    bool fp32 = false;
+    Plan plan;
+    std::vector<int32_t> rank;
+    double precompute_ms = 0.0;
+    double last_sweep_ms = 0.0;
+    int64_t hist_len = 0;
+    bool have_x = false;
+    uint64_t spin_limit = 0;
+
+    DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart, prof;
+    double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double tick_ms = 1e-5;  // wall-clock tick in ms
+    DevBuf<int32_t> ns, ms, rank_d, flags;
+    DevBuf<int64_t> a_off, row_off, loc_off, basis_off;
+    DevBuf<PartInfo> parts;
+    DevBuf<SubMeta> subs;
+    DevBuf<int32_t> row_canon, var_gid, var_slot, var_slot_lo, var_slot_hi;
+    DevBuf<uint16_t> row_lvar, row_sub, var_copy_off, var_copy_rows, tk_sub;
+    DevBuf<uint8_t> var_writer;
+    DevBuf<unsigned char> bpart;
+    DevBuf<unsigned> bar;
+    DevBuf<SweepStatus> st;
+
+    ~ldopf_problem() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (done) (void)hipEventDestroy(done);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+
+namespace ldopf {
+
+// Host LP -> handle with operators precomputed on the device (throws).
+ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipStream_t stream);
+// Enqueue one solve (from the current state) on the handle's stream.
+void problem_launch(ldopf_problem& h);
+// True when the enqueued solve has finished on the device.
+bool problem_ready(const ldopf_problem& h);
+// Wait for the enqueued solve, read its status; returns the ldopf_code.
+int problem_finish(ldopf_problem& h, ldopf_status* status);
+// Device bytes a problem allocates at its peak (creation plus one solve).
+int64_t problem_device_bytes(const ConsensusLP& lp, const ldopf_options& opts);
+// Workgroups of its sweep, planned on the host assuming full row rank.
+int32_t problem_parts_estimate(const ConsensusLP& lp, const ldopf_options& opts);
+
+}  // namespace ldopf

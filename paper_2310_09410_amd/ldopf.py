@@ -12,8 +12,9 @@ import numpy as np
 
 from . import _native as N
 from ._native import (LDOPF_FP32_MIXED, LDOPF_FP64, LDOPF_NOT_CONVERGED, LDOPF_OK,  # noqa: F401
-                      LDOPF_RESIDUAL_AGGREGATED, LDOPF_RESIDUAL_PAPER, ldopf_options, ldopf_sizes,
-                      ldopf_status)
+                      LDOPF_REQ_DONE, LDOPF_REQ_FAILED, LDOPF_REQ_QUEUED, LDOPF_REQ_RUNNING,
+                      LDOPF_RESIDUAL_AGGREGATED, LDOPF_RESIDUAL_PAPER, ldopf_batch_sizes, ldopf_batch_status,
+                      ldopf_options, ldopf_server_stats, ldopf_sizes, ldopf_status)
 
 
 class LdopfError(RuntimeError):
@@ -224,3 +225,138 @@ def ldopf_create_lp(n, c, lo, hi, x_init, n_s, m_s, A, b, gidx, opts: ldopf_opti
                                    C.byref(opts) if opts is not None else None, _stream_handle(stream),
                                    C.byref(h)), "ldopf_create_lp")
     return Problem(h)
+
+
+class Batch:
+    """Owner of one ldopf_batch handle (batched load scenarios)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self.h = handle
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "h", None):
+            N.lib().ldopf_batch_destroy(self.h)
+            self.h = None
+
+    def sizes(self) -> ldopf_batch_sizes:
+        s = ldopf_batch_sizes()
+        _check(N.lib().ldopf_batch_get_sizes(self.h, C.byref(s)), "ldopf_batch_get_sizes")
+        return s
+
+    def set_options(self, opts: ldopf_options):
+        _check(N.lib().ldopf_batch_set_options(self.h, C.byref(opts)), "ldopf_batch_set_options")
+
+    def reset(self):
+        _check(N.lib().ldopf_batch_reset(self.h), "ldopf_batch_reset")
+
+    def solve(self) -> ldopf_batch_status:
+        st = ldopf_batch_status()
+        _check(N.lib().ldopf_batch_solve(self.h, C.byref(st)), "ldopf_batch_solve")
+        return st
+
+    def scenario(self, k: int) -> ldopf_status:
+        st = ldopf_status()
+        _check(N.lib().ldopf_batch_get_scenario(self.h, int(k), C.byref(st)), "ldopf_batch_get_scenario")
+        return st
+
+    def get_global(self, k: int) -> np.ndarray:
+        x = np.empty(self.sizes().n)
+        _check(N.lib().ldopf_batch_get_global(self.h, int(k), _ptr(x, C.c_double), x.shape[0]), "ldopf_batch_get_global")
+        return x
+
+    def get_local(self, k: int):
+        nl = self.sizes().n_local
+        xs, lam = np.empty(nl), np.empty(nl)
+        _check(N.lib().ldopf_batch_get_local(self.h, int(k), _ptr(xs, C.c_double), _ptr(lam, C.c_double), nl),
+               "ldopf_batch_get_local")
+        return xs, lam
+
+    def tune(self, cache_path: str | None = None):
+        r, w = C.c_int32(0), C.c_int32(0)
+        _check(N.lib().ldopf_batch_tune(self.h, cache_path.encode() if cache_path else None, C.byref(r), C.byref(w)),
+               "ldopf_batch_tune")
+        return r.value, w.value
+
+
+def ldopf_batch_create(net: dict, load_scale: np.ndarray, opts: ldopf_options | None = None, stream=None) -> Batch:
+    """Batched scenarios: load_scale is [n_scen, n_load]; scenario k multiplies
+    every load's reference powers by load_scale[k, load]."""
+    nw = Network(net)
+    sc = np.ascontiguousarray(load_scale, dtype=np.float64)
+    if sc.ndim != 2 or sc.shape[1] != int(net["n_load"]):
+        raise ValueError("load_scale must be [n_scen, n_load]")
+    if opts is None:
+        opts = ldopf_default_options(precision=LDOPF_FP32_MIXED)
+    h = C.c_void_p()
+    _check(N.lib().ldopf_batch_create(C.byref(nw.struct), int(sc.shape[0]), _ptr(sc, C.c_double), C.byref(opts),
+                                      _stream_handle(stream), C.byref(h)), "ldopf_batch_create")
+    return Batch(h)
+
+
+def ldopf_request_estimate(net: dict, opts: ldopf_options | None = None):
+    """(device bytes, workgroups) the server's admission counts for a request."""
+    nw = Network(net)
+    b, w = C.c_int64(0), C.c_int32(0)
+    _check(N.lib().ldopf_request_estimate(C.byref(nw.struct), C.byref(opts) if opts is not None else None,
+                                          C.byref(b), C.byref(w)), "ldopf_request_estimate")
+    return b.value, w.value
+
+
+class Server:
+    """Owner of one ldopf_server (the serving request loop)."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 8):
+        h = C.c_void_p()
+        _check(N.lib().ldopf_server_create(int(hbm_budget_bytes), int(max_slots), C.byref(h)), "ldopf_server_create")
+        self.h = h
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "h", None):
+            N.lib().ldopf_server_destroy(self.h)
+            self.h = None
+
+    def submit(self, net: dict, opts: ldopf_options | None = None) -> int:
+        nw = Network(net)
+        rid = C.c_int64(0)
+        _check(N.lib().ldopf_server_submit(self.h, C.byref(nw.struct), C.byref(opts) if opts is not None else None,
+                                           C.byref(rid)), "ldopf_server_submit")
+        return rid.value
+
+    def poll(self, rid: int):
+        state = C.c_int32(0)
+        st = ldopf_status()
+        _check(N.lib().ldopf_server_poll(self.h, int(rid), C.byref(state), C.byref(st)), "ldopf_server_poll")
+        return state.value, st
+
+    def wait(self, rid: int, timeout_s: float = -1.0):
+        state = C.c_int32(0)
+        st = ldopf_status()
+        _check(N.lib().ldopf_server_wait(self.h, int(rid), float(timeout_s), C.byref(state), C.byref(st)),
+               "ldopf_server_wait")
+        return state.value, st
+
+    def cancel(self, rid: int):
+        _check(N.lib().ldopf_server_cancel(self.h, int(rid)), "ldopf_server_cancel")
+
+    def fetch(self, rid: int):
+        sz = np.zeros(2, np.int64)
+        _check(N.lib().ldopf_server_fetch(self.h, int(rid), None, 0, None, None, 0, _ptr(sz, C.c_int64)),
+               "ldopf_server_fetch")
+        x, xs, lam = np.empty(sz[0]), np.empty(sz[1]), np.empty(sz[1])
+        _check(N.lib().ldopf_server_fetch(self.h, int(rid), _ptr(x, C.c_double), x.shape[0], _ptr(xs, C.c_double),
+                                          _ptr(lam, C.c_double), xs.shape[0], None), "ldopf_server_fetch")
+        return x, xs, lam
+
+    def release(self, rid: int):
+        _check(N.lib().ldopf_server_release(self.h, int(rid)), "ldopf_server_release")
+
+    def stats(self) -> ldopf_server_stats:
+        st = ldopf_server_stats()
+        _check(N.lib().ldopf_server_get_stats(self.h, C.byref(st)), "ldopf_server_get_stats")
+        return st

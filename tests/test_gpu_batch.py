@@ -1,0 +1,111 @@
+"""GPU parity of batched load scenarios: every scenario of a batch against an
+oracle solve of the network with that scenario's loads, alone and in the mix.
+
+Batched sweeps run in the FP32-mixed form, so the bar is 1e-4 relative
+(rel_err) on x, x_s at a fixed number of sweeps and on the objective at
+convergence. The stopping sweep itself is not held to the oracle's: near the
+stop the dual test compares per-copy changes of about 1e-7 on values near 1,
+which is FP32's resolution, so the sweep at which an FP32 run first passes
+the test depends on rounding order (a float32 emulation of the same scenario
+stops 12% later with one valid operator factorization and at the FP64 sweep
+with another). It is held within 25%, and the returned state must pass the
+test.
+"""
+import numpy as np
+import pytest
+
+from conftest import feeder, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(net, f, **kw):
+    from oracle import admm, model
+    from synth import scale_loads
+    return admm.solve(model.decompose(scale_loads(net, f)), **kw)
+
+
+def _factors(net, n, seed):
+    from synth import scenario_factors
+    return scenario_factors(net, n, base_seed=seed)
+
+
+def test_batch_classes_and_sizes(gpu):
+    P = gpu
+    net = feeder("123")
+    f = _factors(net, 8, 77)
+    b = P.ldopf_batch_create(net, f)
+    s = b.sizes()
+    assert s.n_scen == 8 and s.n_scen_padded == 64
+    assert s.n_mfma_subsystems > 0 and s.n_vector_subsystems > 0
+    assert s.n_mfma_subsystems + s.n_vector_subsystems == s.n_sub
+
+
+@pytest.mark.parametrize("name", ["13", "123"])
+def test_batch_converged_matches_oracle(gpu, name):
+    P = gpu
+    net = feeder(name)
+    f = _factors(net, 6, 1000 + len(name))
+    b = P.ldopf_batch_create(net, f)
+    st = b.solve()
+    assert st.n_converged == 6 and st.code == 0
+    for k in range(6):
+        ref = _oracle(net, f[k])
+        sk = b.scenario(k)
+        assert sk.converged
+        assert sk.pres <= sk.eps_prim and sk.dres <= sk.eps_dual
+        assert abs(sk.iterations - ref.iters) <= 0.25 * ref.iters, (k, sk.iterations, ref.iters)
+        x = b.get_global(k)
+        obj = float(ref.prep.lp.c @ x)
+        assert abs(obj - ref.objective) / max(1.0, abs(ref.objective)) <= 1e-4
+        assert rel_err(x, ref.x) <= 1e-3  # converged iterates, FP32 path vs FP64 path
+
+
+def test_batch_fixed_sweeps_match_oracle(gpu):
+    P = gpu
+    net = feeder("123")
+    f = _factors(net, 5, 31)
+    T = 150
+    b = P.ldopf_batch_create(net, f, P.ldopf_default_options(precision=1, max_iter=T, check_termination=0))
+    st = b.solve()
+    assert st.sweeps == T
+    for k in range(5):
+        ref = _oracle(net, f[k], max_iter=T, check=False)
+        xs, lam = b.get_local(k)
+        assert b.scenario(k).iterations == T
+        assert rel_err(b.get_global(k), ref.x) <= 1e-4
+        assert rel_err(xs, ref.xs) <= 1e-4
+
+
+def test_batch_alone_equals_in_the_mix(gpu):
+    P = gpu
+    net = feeder("123")
+    f = _factors(net, 9, 5)
+    opts = P.ldopf_default_options(precision=1, rows_per_part=128)
+    mix = P.ldopf_batch_create(net, f, opts)
+    mix.solve()
+    alone = P.ldopf_batch_create(net, f[4:5], opts)
+    alone.solve()
+    assert mix.scenario(4).iterations == alone.scenario(0).iterations
+    np.testing.assert_array_equal(mix.get_global(4), alone.get_global(0))
+    xa, la = alone.get_local(0)
+    xm, lm = mix.get_local(4)
+    np.testing.assert_array_equal(xa, xm)
+    np.testing.assert_array_equal(la, lm)
+
+
+def test_batch_tuner_keeps_results(gpu, tmp_path):
+    P = gpu
+    net = feeder("123")
+    f = _factors(net, 4, 9)
+    opts = P.ldopf_default_options(precision=1, max_iter=100, check_termination=0)
+    a = P.ldopf_batch_create(net, f, opts)
+    a.solve()
+    b = P.ldopf_batch_create(net, f, opts)
+    cache = str(tmp_path / "tune.txt")
+    r, w = b.tune(cache)
+    assert r in (64, 128, 256, 512) and w in (256, 1024, 4096)
+    assert open(cache).read().strip()
+    b.solve()
+    for k in range(4):
+        np.testing.assert_array_equal(a.get_global(k), b.get_global(k))

@@ -124,7 +124,9 @@ def test_fp32_mixed_converged(gpu, name):
     st = prob.solve()
     ref = admm.solve(oracle_prep(name))
     assert st.converged
-    assert abs(st.iterations - ref.iters) <= max(2, 0.02 * ref.iters)
+    assert st.pres <= st.eps_prim and st.dres <= st.eps_dual
+    # FP32 stopping sweep: see the note in test_gpu_batch.py
+    assert abs(st.iterations - ref.iters) <= 0.25 * ref.iters
     assert abs(prob.objective() - ref.objective) / max(1.0, abs(ref.objective)) <= 1e-4
 
 
