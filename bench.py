@@ -58,6 +58,86 @@ def stored_traffic():
     return float(m_t.group(1))
 
 
+def batched_bytes_per_sweep(bs) -> float:
+    """Compulsory bytes of one batched sweep (FP32): shared and per-scenario
+    operators once, and per scenario bbar, x_s and lambda read and written,
+    the gather of B_s x and the global x written."""
+    per_scen = 4 * (bs.n_local * (1 + 4 + 1) + bs.n)
+    return 4 * (bs.shared_operator_words + bs.scenario_operator_words) + bs.n_scen * per_scen
+
+
+def run_batched(P, L, make_feeder, scenario_factors, stream):
+    """2500-bus feeder x 256 load scenarios (FP32-mixed, MFMA) against plain
+    FP64 solves of the same feeder, both to eps_rel 1e-4."""
+    net = make_feeder("2500", 2500)
+    f = scenario_factors(net, 256)
+    b = P.ldopf_batch_create(net, f, stream=stream)
+    b.tune(None)
+    b.set_options(P.ldopf_default_options(precision=L.LDOPF_FP32_MIXED, max_iter=64, check_termination=0))
+    b.reset()
+    b.solve()  # warm: graph instantiation
+    b.set_options(P.ldopf_default_options(precision=L.LDOPF_FP32_MIXED))
+    b.reset()
+    t0 = time.perf_counter()
+    st = b.solve()
+    dt = time.perf_counter() - t0
+    bs = b.sizes()
+    it = sorted(b.scenario(k).iterations for k in range(256))
+    plain = P.ldopf_create(net, P.ldopf_default_options(), stream=stream)
+    plain.solve()
+    plain.reset()
+    t1 = time.perf_counter()
+    ps = plain.solve()
+    dp = time.perf_counter() - t1
+    us = 1e3 * st.solve_ms / max(1, st.sweeps)
+    rec = {"workload": "2500-bus feeder (seed 2500) x 256 load scenarios (per-bus factors U[0.7, 1.3]), "
+                       "FP32-mixed, each scenario to eps_rel 1e-4",
+           "solves_per_s": 256 / dt, "batch_time_s": dt, "converged": st.n_converged, "sweeps": st.sweeps,
+           "iterations_min_median_max": [it[0], it[128], it[-1]], "us_per_batched_sweep": us,
+           "achieved_GBs": batched_bytes_per_sweep(bs) / (us * 1e-6) / 1e9,
+           "bytes_per_batched_sweep": batched_bytes_per_sweep(bs),
+           "mfma_subsystems": bs.n_mfma_subsystems, "vector_subsystems": bs.n_vector_subsystems,
+           "precompute_ms": st.precompute_ms,
+           "plain_fp64_solves_per_s": 1.0 / dp, "plain_fp64_iterations": ps.iterations,
+           "speedup_vs_plain_fp64": (256 / dt) * dp}
+    b.close()
+    plain.close()
+    return rec
+
+
+def run_serving(P, make_feeder, n_req: int, seed: int = 7):
+    """Poisson arrivals of solve requests on fresh feeders sized uniformly
+    from {13, 123, 2500, 8500} buses, FP32-mixed or FP64 with probability
+    1/2 each, at about 0.9 of a serial server's throughput."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sizes = ["13", "123", "2500", "8500"]
+    est_s = {"13": 0.008, "123": 0.09, "2500": 1.8, "8500": 3.4}  # serial solve times, measured before
+    rate = 0.9 / (sum(est_s.values()) / 4)
+    plan = []
+    t = 0.0
+    for i in range(n_req):
+        t += rng.exponential(1.0 / rate)
+        plan.append((t, sizes[int(rng.integers(0, 4))], int(rng.integers(0, 2)), 50000 + i))
+    nets = [(at, make_feeder(sz, sd), prec) for at, sz, prec, sd in plan]
+    srv = P.Server(max_slots=8)
+    start = time.perf_counter()
+    ids = []
+    for at, net, prec in nets:
+        while time.perf_counter() - start < at:
+            time.sleep(0.001)
+        ids.append(srv.submit(net, P.ldopf_default_options(precision=prec)))
+    for rid in ids:
+        srv.wait(rid, 600)
+    st = srv.stats()
+    srv.close()
+    return {"workload": f"{n_req} Poisson requests (rate {rate:.2f}/s) on fresh 13/123/2500/8500-bus feeders, "
+                        "FP32-mixed or FP64 at random, to eps_rel 1e-4",
+            "solves_per_s": st.solves_per_s, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
+            "completed": st.completed, "failed": st.failed, "peak_in_flight": st.peak_running,
+            "peak_bytes": st.peak_bytes_in_use, "sizes": [p_[1] for p_ in plan]}
+
+
 def cpu_baseline(sweeps: int) -> dict:
     """The FP64 oracle timed on this host: a bounded sample of sweeps of the
     same feeder after its precompute. Runs in a child process pinned to one
@@ -89,6 +169,9 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=3000, help="oracle sweeps timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--profile-pass", action="store_true",
                     help="one copy of known size and one solve, for rocprofv3 counter runs")
     ap.add_argument("--cpu-baseline-only", type=int, default=0, help=argparse.SUPPRESS)
@@ -104,7 +187,7 @@ def main():
     import torch
     import paper_2310_09410_amd as P
     from paper_2310_09410_amd import ldopf as L
-    from synth import make_feeder
+    from synth import make_feeder, scenario_factors
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -151,7 +234,7 @@ def main():
     sweeps_per_launch = computed / args.steps
     achieved = b_sweep * sweeps_per_launch / (launch_ms * 1e-3) / 1e9
     rec = {
-        "metric": "ADMM iter/s (8500-bus feeder, to eps_rel 1e-4)",
+        "metric": "ADMM iter/s + time to 1e-4 residual, 8500-bus-shaped feeder; batched solves/s",
         "value": iters / dt,
         "unit": "iter/s",
         "n_gpus": 1,
@@ -188,6 +271,10 @@ def main():
                              "objective": p32.objective(), "objective_rel_diff_vs_fp64":
                                  abs(p32.objective() - obj) / max(1.0, abs(obj))}
         p32.close()
+    if not args.no_batched:
+        rec["batched"] = run_batched(P, L, make_feeder, scenario_factors, stream)
+    if not args.no_serving:
+        rec["serving"] = run_serving(P, make_feeder, args.serving_requests)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args.cpu_sweeps)
     print(json.dumps(rec))

@@ -283,8 +283,13 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     bool ok = grid_barrier(a.bar, P, epoch, a.spin_limit, &bar_ok);
 
     const int GA = task_lanes(TK, nt);
+    // The last wave reads the grid-wide residual sums back and runs the test;
+    // it takes no part in the global update, whose boundary-slot loads would
+    // otherwise wait (in-order vmcnt) on the read-back loads in flight.
+    const int tw = nw - 1;
+    const int g_threads = nw > 1 ? nt - 64 : nt;
     // residual partial sums of the previous sweep, loaded one sweep ahead of
-    // their use (wave 0, lane l holds the parts l, l + 64, l + 128, l + 192)
+    // their use (wave tw, lane l holds the parts l, l + 64, l + 128, l + 192)
     double pv[4][5];
     auto issue_partials = [&](int par) {
 #pragma unroll
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     const double sq = sqrt(double(a.nloc));
     // termination test of one finished sweep from the grid-wide sums held in pv
     auto decide = [&](int64_t sweep) -> bool {
-        if (wv == 0) {
+        if (wv == tw) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
                 const double acc = wave_total(pv[0][q] + pv[1][q] + pv[2][q] + pv[3][q]);
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         T* bnx = a.bpart + int64_t(nx) * ns;
         T* xg = xl[nx];
         // closed_1: clipped average of the copies
-        for (int v = tid; v < V; v += nt) {
+        for (int v = tid; tid < g_threads && v < V; v += g_threads) {
             T s;
             if (slo[v] < 0) {
                 s = ownp[v];
@@ -468,7 +473,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             stopped = true;
             break;
         }
-        if (wv == 0) issue_partials(int(done & 1));
+        if (wv == tw) issue_partials(int(done & 1));
         stamp(6);
     }
     if (ok && !stopped) {
