@@ -308,7 +308,7 @@ typedef struct ldopf_batch_sizes {
     int64_t n_vector_subsystems;            /* per-scenario operator, rank form */
     int64_t scenario_operator_words;        /* FP32 words of per-scenario operators */
     int64_t shared_operator_words;          /* FP32 words of shared operators */
-    int32_t rows_per_chunk, waves_per_tile; /* tuning of the local update */
+    int32_t rows_per_chunk, blocks_per_tile; /* tuning of the local update */
     int32_t graph_sweeps;                   /* sweeps per captured HIP graph */
     int32_t pad;
 } ldopf_batch_sizes;
@@ -318,7 +318,7 @@ typedef struct ldopf_batch_sizes {
  * load_scale: [n_scen x n_load] row-major host array (finite; nullable when
  * n_load = 0). 1 <= n_scen <= 1024. opts->precision must be
  * LDOPF_FP32_MIXED (else LDOPF_UNSUPPORTED); rho is fixed at creation;
- * rows_per_part sets the rows per chunk of the local update (0: 256). The
+ * rows_per_part sets the rows per chunk of the local update (0: 64). The
  * batch runs on a stream of its own, ordered after the caller's stream. */
 LDOPF_API int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* load_scale,
                                  const ldopf_options* opts, void* stream, ldopf_batch** out);
@@ -336,12 +336,12 @@ LDOPF_API int ldopf_batch_get_global(const ldopf_batch* h, int32_t scen, double*
 LDOPF_API int ldopf_batch_get_local(const ldopf_batch* h, int32_t scen, double* xs, double* lam, int64_t cap);
 LDOPF_API int ldopf_batch_get_sizes(const ldopf_batch* h, ldopf_batch_sizes* out);
 /* Autotuner: time short runs of the local update over rows per chunk and
- * waves per scenario tile, keep the fastest, and remember it in a text cache
+ * blocks per 64-scenario tile, keep the fastest, and remember it in a text cache
  * file keyed by device, network shape and batch size (cache_path nullable:
  * no cache). Resets the batch. Results do not depend on the choice except
  * for the summation order of the residual sums. */
 LDOPF_API int ldopf_batch_tune(ldopf_batch* h, const char* cache_path, int32_t* rows_per_chunk,
-                               int32_t* waves_per_tile);
+                               int32_t* blocks_per_tile);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop for OPF solves of differing feeders.

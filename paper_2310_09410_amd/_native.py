@@ -86,7 +86,7 @@ class ldopf_batch_sizes(C.Structure):
         ("n", C.c_int64), ("n_sub", C.c_int64), ("n_local", C.c_int64), ("n_scen", C.c_int32),
         ("n_scen_padded", C.c_int32), ("n_mfma_subsystems", C.c_int64), ("n_vector_subsystems", C.c_int64),
         ("scenario_operator_words", C.c_int64), ("shared_operator_words", C.c_int64),
-        ("rows_per_chunk", C.c_int32), ("waves_per_tile", C.c_int32), ("graph_sweeps", C.c_int32),
+        ("rows_per_chunk", C.c_int32), ("blocks_per_tile", C.c_int32), ("graph_sweeps", C.c_int32),
         ("pad", C.c_int32),
     ]
 

@@ -135,7 +135,7 @@ void build_device(ldopf_problem& h) {
 
     h.plan = make_plan(lp, h.rank, h.fp32, h.opts.rows_per_part, h.opts.block_threads, cus, lds_optin);
     const Plan& pl = h.plan;
-    if (pl.n_parts > kMaxParts) fail(LDOPF_UNSUPPORTED, "too many workgroups for the grid barrier");
+    if (pl.n_parts > kMaxParts) fail(LDOPF_UNSUPPORTED, "more than " + std::to_string(kMaxParts) + " sweep workgroups");
     hip_check(prepare_sweep(h.fp32, size_t(pl.lds_bytes)), "sweep LDS attribute");
     int per_cu = 0;
     hip_check(sweep_occupancy(h.fp32, pl.block_threads, size_t(pl.lds_bytes), &per_cu), "sweep occupancy");
@@ -167,8 +167,7 @@ void build_device(ldopf_problem& h) {
     h.lam.alloc(lp.gidx.size(), "lambda");
     h.x.alloc(lp.n, "x");
     h.bpart.alloc(size_t(2) * std::max(pl.n_slots, 1) * (h.fp32 ? 4 : 8), "boundary slots");
-    h.rpart.alloc(size_t(2) * pl.n_parts * 8, "residual slots");
-    h.bar.alloc(kBarWords, "barrier");
+    h.rpart.alloc(size_t(kRing) * pl.n_parts * 8, "residual slots");
     h.st.alloc(1, "status");
     h.prof.alloc(8, "phase times");
     init_state(h);
@@ -201,7 +200,6 @@ SweepArgs<T> sweep_args(ldopf_problem& h) {
     a.x = h.x.p;
     a.bpart = reinterpret_cast<T*>(h.bpart.p);
     a.rpart = h.rpart.p;
-    a.bar = h.bar.p;
     a.hist = h.hist.p;
     a.hist_cap = h.opts.history ? int64_t(h.hist.count / 4) : 0;
     a.st = h.st.p;
@@ -327,8 +325,8 @@ int64_t problem_device_bytes(const ConsensusLP& lp, const ldopf_options& o) {
     for (int32_t v : lp.ns) nn += int64_t(v) * v;
     const int64_t hist = o.history ? std::min<int64_t>(std::max<int64_t>(o.max_iter, 1), int64_t(1) << 22) * 32 : 32;
     int64_t bytes = 8 * int64_t(lp.A.size() + lp.b.size()) + 8 * 2 * nn + 8 * nloc * 3 + 8 * n * 5 +
-                    S * (4 * 4 + 8 * 4 + 32) + nloc * (4 + 2 * 4 + 4 * 4 + 1) + 2 * 8 * nloc + 2 * 1024 * 64 +
-                    kBarWords * 4 + hist;
+                    S * (4 * 4 + 8 * 4 + 32) + nloc * (4 + 2 * 4 + 4 * 4 + 1) + 2 * 8 * nloc * 4 +
+                    int64_t(kRing) * kMaxParts * 64 + hist;
     return bytes + 48 * 4096;  // allocation granularity of about 48 buffers
 }
 

@@ -44,8 +44,9 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kTile = 64;        // scenarios per wave
-constexpr int kZS = kTile + 1;   // padded LDS row stride of the MFMA kernel
+constexpr int kTile = 64;  // scenarios per wave
+constexpr int kZS = 80;    // LDS row stride (floats) of the local update
+constexpr int kVPW = 4;    // variables per wave in the global update
 
 struct PrecomputeBatchArgs {
     int64_t S, nloc, words;
@@ -88,6 +89,37 @@ struct PackArgs {
     int32_t* flag;            // bit 1: rank changed with the scale, bit 2: inconsistent rows
 };
 
+// Read-only tables of a kernel read through the constant address space, so
+// that uniform reads become scalar loads.
+template <typename T>
+using CPtr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ inline CPtr<T> as_const(const T* p) {
+    return (CPtr<T>)(p);
+}
+
+// One subsystem of the local update: n_s, class (0 shared operator on MFMA,
+// 1 per-scenario rank form), K_s and mode of the rank form, first copy, and
+// the offset of its shared Abar_s (class 0, floats) or of its first W row
+// (class 1, units of the padded scenario count).
+struct LocalMeta {
+    int32_t n, cls, K, mode;
+    int64_t row0, off;
+};
+static_assert(sizeof(LocalMeta) == 32, "LocalMeta layout");
+
+__device__ inline LocalMeta load_meta(CPtr<int32_t> t, int q) {
+    const CPtr<int32_t> e = t + 8 * q;
+    LocalMeta m;
+    m.n = e[0];
+    m.cls = e[1];
+    m.K = e[2];
+    m.mode = e[3];
+    m.row0 = int64_t(uint32_t(e[4])) | (int64_t(e[5]) << 32);
+    m.off = int64_t(uint32_t(e[6])) | (int64_t(e[7]) << 32);
+    return m;
+}
+
 struct BatchArgs {
     int32_t B, Bp;
     int64_t n, nloc;
@@ -104,23 +136,17 @@ struct BatchArgs {
     float* XS;
     float* LAM;
     const float* BB;
-    // MFMA class
-    int32_t n_mf_chunks;
-    const int32_t* mf_sub;
-    const int32_t* mf_chunk_off;
-    const float* ash;
-    const int64_t* ash_off;
-    // vector class
-    int32_t n_vec_chunks;
-    const int32_t* vec_sub;
-    const int32_t* vec_chunk_off;
-    const float* W;
-    const int64_t* wofs;  // indexed by subsystem
-    const int32_t* vK;
-    const int32_t* vmode;
+    const int4* ell;      // [n] first four copies of each variable, -1 padded
+    // local update: chunks of subsystems, both classes
+    int32_t n_chunks;
+    const int32_t* chunk_off;
+    const LocalMeta* meta;  // per subsystem, in chunk order
+    int32_t nmax, kmax;     // largest n_s, largest K_s of the per-scenario class
+    const float* ash;       // shared FP32 Abar_s
+    const float* W;         // per-scenario rank-form rows
     // residuals and control
     double* part;      // [part_rows][5][Bp]
-    int32_t mf_rows, part_rows;
+    int32_t part_rows;
     int32_t* active;   // [Bp]
     int32_t* conv;     // [Bp]
     int64_t* iters;    // [Bp]
@@ -176,185 +202,250 @@ __global__ __launch_bounds__(256) void batch_pack_kernel(PackArgs a) {
     }
 }
 
-// Global update (closed_1), one thread per (variable, scenario).
+// Global update (closed_1): a wave takes kVPW consecutive variables for one
+// 64-scenario tile. The first four copies of each variable come from a
+// padded table (one 16-byte read per variable) so that all their loads are
+// in flight together; further copies, if any, from the CSR lists. Copies are
+// added in CSR order.
 __global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
     if (a.ctrl[1]) return;
     const int lane = threadIdx.x & 63;
-    const int64_t v = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int64_t v0 = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * kVPW;
     const int sc = blockIdx.y * kTile + lane;
-    if (v >= a.n || !a.active[sc]) return;
+    if (v0 >= a.n || !a.active[sc]) return;
     const float irho = float(1.0 / a.rho);
-    float s = 0.f;
-    for (int q = a.var_off[v]; q < a.var_off[v + 1]; ++q) {
-        const int64_t c = a.var_copy[q];
-        s += a.XS[c * a.Bp + sc] - a.LAM[c * a.Bp + sc] * irho;
-    }
-    float x = (s - a.crho[v]) * a.invN[v];
-    x = x < a.lo[v] ? a.lo[v] : x;
-    x = x > a.hi[v] ? a.hi[v] : x;
-    a.X[v * a.Bp + sc] = x;
-}
-
-// Local + dual update of the MFMA class: Y = Bbar - Abar_s V per 64-scenario
-// tile; rows of Abar_s in 16-row tiles, scenarios in four 16-column tiles.
-// Operand layout of v_mfma_f32_16x16x4f32: lane l holds A[l % 16][l / 16],
-// B[l / 16][l % 16] and D[4 (l / 16) + i][l % 16], i < 4.
-__global__ __launch_bounds__(64) void batch_local_mfma_kernel(BatchArgs a) {
-    if (a.ctrl[1]) return;
-    extern __shared__ __align__(16) float sm[];
-    float* zs = sm;              // [n][kZS]
-    float* ls = sm + 64 * kZS;   // [n][kZS]
-    double* red = reinterpret_cast<double*>(sm + 2 * 64 * kZS);  // [4][64][5]
-    const int lane = threadIdx.x;
-    const int tile = blockIdx.y;
-    const int sc = tile * kTile + lane;
-    const float rho = float(a.rho), irho = float(1.0 / a.rho);
-    double p[4][5];
+    const int64_t Bp = a.Bp;
+    float xs[kVPW][4], lm[kVPW][4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int u = 0; u < kVPW; ++u) {
+        const int64_t v = v0 + u;
+        const int4 e = v < a.n ? a.ell[v] : int4{-1, -1, -1, -1};
+        const int ec[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
-        for (int q = 0; q < 5; ++q) p[nt][q] = 0.0;
-    for (int c = blockIdx.x; c < a.n_mf_chunks; c += gridDim.x) {
-        for (int q = a.mf_chunk_off[c]; q < a.mf_chunk_off[c + 1]; ++q) {
-            const int s = a.mf_sub[q];
-            const int n = a.ns[s];
-            const int64_t row0 = a.loc_off[s];
-            const float* Ab = a.ash + a.ash_off[q];
-            for (int j = 0; j < n; ++j) {
-                zs[j * kZS + lane] = a.X[int64_t(a.gidx[row0 + j]) * a.Bp + sc];
-                ls[j * kZS + lane] = a.LAM[(row0 + j) * a.Bp + sc];
-            }
-            __syncthreads();
-            for (int mt = 0; mt * 16 < n; ++mt) {
-                floatx4 acc[4];
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-                const int ar = mt * 16 + (lane & 15);
-                for (int kk = 0; kk * 4 < n; ++kk) {
-                    const int kc = kk * 4 + (lane >> 4);
-                    const float av = (ar < n && kc < n) ? Ab[ar * n + kc] : 0.f;
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
-                        const int bc = nt * 16 + (lane & 15);
-                        const float bv = kc < n ? zs[kc * kZS + bc] + ls[kc * kZS + bc] * irho : 0.f;
-                        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[nt], 0, 0, 0);
-                    }
-                }
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
-                    const int scl = nt * 16 + (lane & 15);
-                    const int scg = tile * kTile + scl;
-                    const bool on = a.active[scg] != 0;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int row = mt * 16 + 4 * (lane >> 4) + i;
-                        if (row < n) {
-                            const int64_t cr = (row0 + row) * a.Bp + scg;
-                            const float y = a.BB[cr] - acc[nt][i];
-                            const float z = zs[row * kZS + scl];
-                            const float l0 = ls[row * kZS + scl];
-                            const float l1 = l0 + rho * (z - y);
-                            const float xo = a.XS[cr];
-                            if (on) {
-                                a.XS[cr] = y;
-                                a.LAM[cr] = l1;
-                                const double dz = double(z) - double(y), dx = double(y) - double(xo);
-                                p[nt][0] += dz * dz;
-                                p[nt][1] += dx * dx;
-                                p[nt][2] += double(z) * double(z);
-                                p[nt][3] += double(y) * double(y);
-                                p[nt][4] += double(l1) * double(l1);
-                            }
-                        }
-                    }
-                }
-            }
-            __syncthreads();
+        for (int i = 0; i < 4; ++i) {
+            xs[u][i] = ec[i] >= 0 ? a.XS[int64_t(ec[i]) * Bp + sc] : 0.f;
+            lm[u][i] = ec[i] >= 0 ? a.LAM[int64_t(ec[i]) * Bp + sc] : 0.f;
         }
     }
-    // lanes l, l + 16, l + 32, l + 48 hold partial sums of the same scenarios
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int u = 0; u < kVPW; ++u) {
+        const int64_t v = v0 + u;
+        if (v >= a.n) break;
+        const int q0 = a.var_off[v], q1 = a.var_off[v + 1];
+        float s = xs[u][0] - lm[u][0] * irho;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) red[((lane >> 4) * 64 + nt * 16 + (lane & 15)) * 5 + q] = p[nt][q];
-    __syncthreads();
-    double* out = a.part + int64_t(blockIdx.x) * 5 * a.Bp;
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-        out[q * a.Bp + sc] = ((red[(0 * 64 + lane) * 5 + q] + red[(1 * 64 + lane) * 5 + q]) +
-                              red[(2 * 64 + lane) * 5 + q]) + red[(3 * 64 + lane) * 5 + q];
+        for (int i = 1; i < 4; ++i)
+            if (q0 + i < q1) s += xs[u][i] - lm[u][i] * irho;
+        for (int q = q0 + 4; q < q1; ++q) {
+            const int64_t c = a.var_copy[q];
+            s += a.XS[c * Bp + sc] - a.LAM[c * Bp + sc] * irho;
+        }
+        float x = (s - a.crho[v]) * a.invN[v];
+        x = x < a.lo[v] ? a.lo[v] : x;
+        x = x > a.hi[v] ? a.hi[v] : x;
+        a.X[v * Bp + sc] = x;
+    }
 }
 
-// Local + dual update of the vector class: per scenario, rank form
-// y = bbar + v - W'(W v) (mode 1) or bbar + W'(W v) (mode 0) with this
-// scenario's W. One lane per scenario.
-__global__ __launch_bounds__(64) void batch_local_vec_kernel(BatchArgs a, int nmax) {
+// Local + dual update of both classes, four waves per block on one
+// 64-scenario tile (lane = scenario). Rows j of a subsystem belong to wave
+// j % 4; a wave keeps its rows' z, lambda and old x_s in registers (at most
+// RPW rows, so n_s <= 4 RPW) and stages v = z + lambda / rho and bbar, then
+// the projection y, in LDS ([row][kZS], kZS = 80 floats: rows four apart fall on
+// disjoint halves of the 32 banks, so the MFMA operand reads do not
+// conflict).
+//   shared-operator class: Y = Bbar - Abar_s V on MFMA; wave w takes the
+//     16-row tiles w, w + 4, ... of Abar_s against the four 16-scenario tiles;
+//     v_mfma_f32_16x16x4f32 operand layout: lane l holds A[l % 16][l / 16],
+//     B[l / 16][l % 16] and D[4 (l / 16) + i][l % 16], i < 4;
+//   per-scenario class: t = W v (wave w takes basis rows w, w + 4, ...), then
+//     y = bbar + v - W't (mode 1) or bbar + W't (mode 0) per row.
+// Then lambda += rho (z - y), and the FP64 residual sums per scenario.
+template <int RPW>
+__global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
     if (a.ctrl[1]) return;
     extern __shared__ __align__(16) float sm[];
-    float* zs = sm;               // [nmax][64]
-    float* ls = sm + nmax * 64;   // [nmax][64]
-    float* ts = sm + 2 * nmax * 64;  // [nmax][64]
-    const int lane = threadIdx.x;
+    float* Vs = sm;                         // [nmax][kZS]
+    float* Ys = Vs + a.nmax * kZS;          // [nmax][kZS]
+    float* Ts = Ys + a.nmax * kZS;          // [kmax][kZS]
+    float* As = Ts + a.kmax * kZS;          // [nmax * nmax] shared operator
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int Bp = a.Bp;
     const int sc = blockIdx.y * kTile + lane;
     const bool on = a.active[sc] != 0;
     const float rho = float(a.rho), irho = float(1.0 / a.rho);
-    double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;
-    for (int c = blockIdx.x; c < a.n_vec_chunks; c += gridDim.x) {
-        for (int q = a.vec_chunk_off[c]; q < a.vec_chunk_off[c + 1]; ++q) {
-            const int s = a.vec_sub[q];
-            const int n = a.ns[s], K = a.vK[s], mode = a.vmode[s];
-            const int64_t row0 = a.loc_off[s];
-            const float* W = a.W + a.wofs[s] * a.Bp + sc;
-            for (int j = 0; j < n; ++j) {
-                zs[j * 64 + lane] = a.X[int64_t(a.gidx[row0 + j]) * a.Bp + sc];
-                ls[j * 64 + lane] = a.LAM[(row0 + j) * a.Bp + sc];
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
+    // read-only tables through the constant address space (scalar loads)
+    const CPtr<int32_t> chunk_off = as_const(a.chunk_off);
+    const CPtr<int32_t> meta = as_const(reinterpret_cast<const int32_t*>(a.meta));
+    const CPtr<int32_t> gidx = as_const(a.gidx);
+    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+        const int q1 = chunk_off[c + 1];
+        int q = chunk_off[c];
+        LocalMeta m = load_meta(meta, q);
+        for (; q < q1; ++q) {
+            // the next subsystem's metadata is loaded one subsystem ahead
+            const LocalMeta mn = load_meta(meta, q + 1 < q1 ? q + 1 : q);
+            const int n = m.n;
+            const int64_t row0 = m.row0;
+            const float* LAMb = a.LAM + row0 * Bp;
+            const float* XSb = a.XS + row0 * Bp;
+            const float* BBb = a.BB + row0 * Bp;
+            // row indices first, then every row load of the wave before any
+            // use; rows past n_s repeat the last row (loaded, never used) so
+            // that no branch separates the loads
+            int gi[RPW];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) gi[r] = gidx[row0 + min(wv + 4 * r, n - 1)];
+            float z[RPW], l0[RPW], xo[RPW], bb[RPW];
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int o = min(wv + 4 * r, n - 1) * Bp + sc;
+                z[r] = a.X[gi[r] * Bp + sc];
+                l0[r] = LAMb[o];
+                xo[r] = XSb[o];
+                bb[r] = BBb[o];
             }
-            for (int k = 0; k < K; ++k) {
-                float t = 0.f;
-                for (int j = 0; j < n; ++j) t += W[int64_t(k * n + j) * a.Bp] * (zs[j * 64 + lane] + ls[j * 64 + lane] * irho);
-                ts[k * 64 + lane] = t;
+            if (m.cls == 0) {
+                const float* Ab = a.ash + m.off;
+                for (int i = tid; i < n * n; i += 256) As[i] = Ab[i];
             }
-            for (int j = 0; j < n; ++j) {
-                float acc = 0.f;
-                for (int k = 0; k < K; ++k) acc += W[int64_t(k * n + j) * a.Bp] * ts[k * 64 + lane];
-                const float z = zs[j * 64 + lane], l0 = ls[j * 64 + lane];
-                const float vj = z + l0 * irho;
-                const int64_t cr = (row0 + j) * a.Bp + sc;
-                const float y = mode ? a.BB[cr] + (vj - acc) : a.BB[cr] + acc;
-                const float l1 = l0 + rho * (z - y);
-                const float xo = a.XS[cr];
-                if (on) {
-                    a.XS[cr] = y;
-                    a.LAM[cr] = l1;
-                    const double dz = double(z) - double(y), dx = double(y) - double(xo);
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int j = wv + 4 * r;
+                if (j < n) {
+                    Vs[j * kZS + lane] = z[r] + l0[r] * irho;
+                    Ys[j * kZS + lane] = bb[r];
+                }
+            }
+            __syncthreads();
+            if (m.cls == 0) {
+                for (int mt = wv; mt * 16 < n; mt += 4) {
+                    floatx4 acc[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    const int ar = mt * 16 + (lane & 15);
+                    for (int kk = 0; kk * 4 < n; ++kk) {
+                        const int kc = kk * 4 + (lane >> 4);
+                        const bool in = kc < n;
+                        const float av = (ar < n && in) ? As[ar * n + kc] : 0.f;
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const float bv = in ? Vs[kc * kZS + nt * 16 + (lane & 15)] : 0.f;
+                            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[nt], 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int row = mt * 16 + 4 * (lane >> 4) + i;
+                            if (row < n) Ys[row * kZS + nt * 16 + (lane & 15)] -= acc[nt][i];
+                        }
+                }
+            } else {
+                const int K = m.K, mode = m.mode;
+                const float* Wb = a.W + m.off * Bp;
+                const int nB = n * Bp;
+                for (int k = wv; k < K; k += 4) {
+                    const int o0 = k * nB + sc;
+                    float t[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    int j = 0;
+                    for (; j + 8 <= n; j += 8) {
+                        float w[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) w[u] = Wb[o0 + (j + u) * Bp];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) t[u] += w[u] * Vs[(j + u) * kZS + lane];
+                    }
+                    for (; j < n; ++j) t[0] += Wb[o0 + j * Bp] * Vs[j * kZS + lane];
+                    Ts[k * kZS + lane] = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+                }
+                __syncthreads();
+                for (int j = wv; j < n; j += 4) {
+                    const int o0 = j * Bp + sc;
+                    float u[4] = {0.f, 0.f, 0.f, 0.f};
+                    int k = 0;
+                    for (; k + 4 <= K; k += 4) {
+                        float w[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) w[e] = Wb[o0 + (k + e) * nB];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) u[e] += w[e] * Ts[(k + e) * kZS + lane];
+                    }
+                    for (; k < K; ++k) u[0] += Wb[o0 + k * nB] * Ts[k * kZS + lane];
+                    const float acc = (u[0] + u[1]) + (u[2] + u[3]);
+                    const float vj = Vs[j * kZS + lane];
+                    const float bj = Ys[j * kZS + lane];
+                    Ys[j * kZS + lane] = mode ? bj + (vj - acc) : bj + acc;
+                }
+            }
+            __syncthreads();
+            // dual update and residual sums on the wave's own rows
+            float* XSw = a.XS + row0 * Bp;
+            float* LAMw = a.LAM + row0 * Bp;
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int j = wv + 4 * r;
+                if (j < n && on) {
+                    const int o = j * Bp + sc;
+                    const float y = Ys[j * kZS + lane];
+                    const float l1 = l0[r] + rho * (z[r] - y);
+                    XSw[o] = y;
+                    LAMw[o] = l1;
+                    const double dz = double(z[r]) - double(y), dx = double(y) - double(xo[r]);
                     p0 += dz * dz;
                     p1 += dx * dx;
-                    p2 += double(z) * double(z);
+                    p2 += double(z[r]) * double(z[r]);
                     p3 += double(y) * double(y);
                     p4 += double(l1) * double(l1);
                 }
             }
+            m = mn;
         }
     }
-    double* out = a.part + int64_t(a.mf_rows + blockIdx.x) * 5 * a.Bp;
-    out[0 * a.Bp + sc] = p0;
-    out[1 * a.Bp + sc] = p1;
-    out[2 * a.Bp + sc] = p2;
-    out[3 * a.Bp + sc] = p3;
-    out[4 * a.Bp + sc] = p4;
+    // the four waves' sums of each scenario, in wave order
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(sm);  // [4][5][64]
+    red[(wv * 5 + 0) * 64 + lane] = p0;
+    red[(wv * 5 + 1) * 64 + lane] = p1;
+    red[(wv * 5 + 2) * 64 + lane] = p2;
+    red[(wv * 5 + 3) * 64 + lane] = p3;
+    red[(wv * 5 + 4) * 64 + lane] = p4;
+    __syncthreads();
+    double* out = a.part + int64_t(blockIdx.x) * 5 * Bp;
+    for (int e = tid; e < 5 * 64; e += 256) {
+        const int qq = e >> 6, l = e & 63;
+        out[qq * Bp + blockIdx.y * kTile + l] = ((red[(0 * 5 + qq) * 64 + l] + red[(1 * 5 + qq) * 64 + l]) +
+                                                 red[(2 * 5 + qq) * 64 + l]) +
+                                                red[(3 * 5 + qq) * 64 + l];
+    }
 }
 
-// Residual sums per scenario (fixed order: rows split over 4 waves, then the
-// waves in order), the termination test, the masks; the last block to finish
-// advances the sweep counter and decides whether the batch is done.
-__global__ __launch_bounds__(256) void batch_reduce_kernel(BatchArgs a) {
+// Residual sums per scenario over the local blocks' partial rows (16 waves,
+// wave w adds rows w, w + 16, ...; then the waves in order), the termination
+// test, the masks; the last block to finish advances the sweep counter and
+// decides whether the batch is done.
+__global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
     if (a.ctrl[1]) return;
-    __shared__ double red[4][5][64];
+    __shared__ double red[16][5][64];
     __shared__ int last;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int sc = blockIdx.x * kTile + lane;
     double acc[5] = {0, 0, 0, 0, 0};
-    for (int r = wv; r < a.part_rows; r += 4)
+    int r = wv;
+    for (; r + 16 < a.part_rows; r += 32) {
+        double u[5], w[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            u[q] = a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
+            w[q] = a.part[(int64_t(r + 16) * 5 + q) * a.Bp + sc];
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] += u[q] + w[q];
+    }
+    if (r < a.part_rows)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[q] += a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
 #pragma unroll
@@ -364,7 +455,11 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(BatchArgs a) {
     if (wv == 0) {
         double d[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) d[q] = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
+        for (int q = 0; q < 5; ++q) {
+            double t = 0.0;
+            for (int w = 0; w < 16; ++w) t += red[w][q][lane];
+            d[q] = t;
+        }
         int still = 0;
         if (sc < a.B && a.active[sc]) {
             const double sq = sqrt(double(a.nloc));
@@ -439,15 +534,17 @@ struct ldopf_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t graph_sweeps = 16;
-    int32_t mf_grid = 0, vec_grid = 0, nmax_vec = 0;
+    int32_t grid = 0;         // local-update blocks per scenario tile
+    int32_t nmax = 1, kmax = 1, rpw = 10;
     double precompute_ms = 0.0;
     int64_t n_mf = 0, n_vec = 0;
-    std::vector<int32_t> mf_chunk_off_h, vec_chunk_off_h;
-    std::vector<int32_t> mf_h, vec_h;  // class lists (canonical subsystem ids)
+    std::vector<int32_t> chunk_off_h;
     int32_t rows_per_chunk = 0;
 
-    DevBuf<int32_t> ns, gidx, var_off, var_copy, mf_sub, mf_chunk_off, vec_sub, vec_chunk_off, vK, vmode;
-    DevBuf<int64_t> loc_off, ash_off, wofs, iters, ctrl;
+    DevBuf<int32_t> ns, gidx, var_off, var_copy, chunk_off, cls, vK;
+    DevBuf<LocalMeta> meta;
+    DevBuf<int4> ell;
+    DevBuf<int64_t> loc_off, wofs, iters, ctrl;
     DevBuf<float> crho, lo, hi, invN, X, XS, LAM, BB, ash, W;
     DevBuf<double> x_init, part, res;
     DevBuf<int32_t> active, conv, sflags;
@@ -483,21 +580,16 @@ BatchArgs batch_args(ldopf_batch& h) {
     a.XS = h.XS.p;
     a.LAM = h.LAM.p;
     a.BB = h.BB.p;
-    a.n_mf_chunks = int32_t(h.mf_chunk_off_h.size()) - 1;
-    a.mf_sub = h.mf_sub.p;
-    a.mf_chunk_off = h.mf_chunk_off.p;
+    a.ell = h.ell.p;
+    a.n_chunks = int32_t(h.chunk_off_h.size()) - 1;
+    a.chunk_off = h.chunk_off.p;
+    a.meta = h.meta.p;
+    a.nmax = h.nmax;
+    a.kmax = h.kmax;
     a.ash = h.ash.p;
-    a.ash_off = h.ash_off.p;
-    a.n_vec_chunks = int32_t(h.vec_chunk_off_h.size()) - 1;
-    a.vec_sub = h.vec_sub.p;
-    a.vec_chunk_off = h.vec_chunk_off.p;
     a.W = h.W.p;
-    a.wofs = h.wofs.p;
-    a.vK = h.vK.p;
-    a.vmode = h.vmode.p;
     a.part = h.part.p;
-    a.mf_rows = h.mf_grid;
-    a.part_rows = h.mf_grid + h.vec_grid;
+    a.part_rows = h.grid;
     a.active = h.active.p;
     a.conv = h.conv.p;
     a.iters = h.iters.p;
@@ -512,45 +604,47 @@ BatchArgs batch_args(ldopf_batch& h) {
     return a;
 }
 
-size_t mfma_lds() { return size_t(2 * 64 * kZS) * 4 + size_t(4 * 64 * 5) * 8; }
+size_t local_lds(const ldopf_batch& h) {
+    return std::max<size_t>(size_t((2 * h.nmax + h.kmax) * kZS + h.nmax * h.nmax) * 4, size_t(4 * 5 * 64) * 8);
+}
+
+const void* local_kernel(int rpw) {
+    switch (rpw) {
+        case 10: return reinterpret_cast<const void*>(&batch_local_kernel<10>);
+        case 16: return reinterpret_cast<const void*>(&batch_local_kernel<16>);
+        default: return reinterpret_cast<const void*>(&batch_local_kernel<32>);
+    }
+}
 
 void enqueue_sweep(ldopf_batch& h, const BatchArgs& a) {
     const int tiles = h.Bp / kTile;
-    hipLaunchKernelGGL(batch_global_kernel, dim3(unsigned((a.n + 3) / 4), tiles), dim3(256), 0, h.stream, a);
-    if (h.mf_grid > 0)
-        hipLaunchKernelGGL(batch_local_mfma_kernel, dim3(h.mf_grid, tiles), dim3(64), mfma_lds(), h.stream, a);
-    if (h.vec_grid > 0)
-        hipLaunchKernelGGL(batch_local_vec_kernel, dim3(h.vec_grid, tiles), dim3(64), size_t(3 * h.nmax_vec * 64) * 4,
-                           h.stream, a, h.nmax_vec);
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(tiles), dim3(256), 0, h.stream, a);
+    const int64_t per_block = 4 * kVPW;
+    hipLaunchKernelGGL(batch_global_kernel, dim3(unsigned((a.n + per_block - 1) / per_block), tiles), dim3(256), 0,
+                       h.stream, a);
+    BatchArgs copy = a;
+    void* args[] = {&copy};
+    (void)hipLaunchKernel(local_kernel(h.rpw), dim3(h.grid, tiles), dim3(256), args, local_lds(h), h.stream);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(tiles), dim3(1024), 0, h.stream, a);
 }
 
-// Chunks of a class list: consecutive subsystems up to rows_per_chunk copies.
-std::vector<int32_t> make_chunks(const std::vector<int32_t>& subs, const ConsensusLP& lp, int32_t rows_per_chunk) {
+// Chunks of the subsystem order: consecutive subsystems up to rows_per_chunk copies.
+std::vector<int32_t> make_chunks(const ConsensusLP& lp, int32_t rows_per_chunk) {
     std::vector<int32_t> off{0};
     int64_t rows = 0;
-    for (size_t q = 0; q < subs.size(); ++q) {
-        rows += lp.ns[subs[q]];
+    for (int64_t q = 0; q < lp.S; ++q) {
+        rows += lp.ns[q];
         if (rows >= rows_per_chunk) {
             off.push_back(int32_t(q + 1));
             rows = 0;
         }
     }
-    if (off.back() != int32_t(subs.size())) off.push_back(int32_t(subs.size()));
+    if (off.back() != int32_t(lp.S)) off.push_back(int32_t(lp.S));
     return off;
 }
 
-void set_chunks(ldopf_batch& h, const std::vector<int32_t>& mf, const std::vector<int32_t>& vec, int32_t rows_per_chunk,
-                int32_t waves_per_tile) {
-    h.rows_per_chunk = rows_per_chunk;
-    h.mf_chunk_off_h = make_chunks(mf, h.lp, rows_per_chunk);
-    h.vec_chunk_off_h = make_chunks(vec, h.lp, rows_per_chunk);
-    const int32_t nmf = int32_t(h.mf_chunk_off_h.size()) - 1, nvec = int32_t(h.vec_chunk_off_h.size()) - 1;
-    h.mf_grid = std::min(nmf, waves_per_tile);
-    h.vec_grid = std::min(nvec, waves_per_tile);
-    h.mf_chunk_off.upload(h.mf_chunk_off_h, h.stream, "upload chunks");
-    h.vec_chunk_off.upload(h.vec_chunk_off_h, h.stream, "upload chunks");
-    h.part.alloc(size_t(std::max(1, h.mf_grid + h.vec_grid)) * 5 * h.Bp, "residual partials");
+// The captured graph holds the kernel arguments (options, chunking): drop it
+// whenever they change.
+void drop_graph(ldopf_batch& h) {
     if (h.exec) {
         (void)hipGraphExecDestroy(h.exec);
         h.exec = nullptr;
@@ -559,6 +653,16 @@ void set_chunks(ldopf_batch& h, const std::vector<int32_t>& mf, const std::vecto
         (void)hipGraphDestroy(h.graph);
         h.graph = nullptr;
     }
+}
+
+void set_chunks(ldopf_batch& h, int32_t rows_per_chunk, int32_t blocks_per_tile) {
+    h.rows_per_chunk = rows_per_chunk;
+    h.chunk_off_h = make_chunks(h.lp, rows_per_chunk);
+    const int32_t nch = int32_t(h.chunk_off_h.size()) - 1;
+    h.grid = std::max(1, std::min(nch, blocks_per_tile));
+    h.chunk_off.upload(h.chunk_off_h, h.stream, "upload chunks");
+    h.part.alloc(size_t(h.grid) * 5 * h.Bp, "residual partials");
+    drop_graph(h);
 }
 
 void build_graph(ldopf_batch& h) {
@@ -737,7 +841,7 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             std::vector<int64_t> wofs(S, 0), ash_off_s(S, 0);
             std::vector<int32_t> mf, vec;
             int64_t wrows = 0, ash_words = 0;
-            int32_t nmax_vec = 1;
+            int32_t nmax = 1, kmax = 1;
             for (int64_t i = 0; i < S; ++i) {
                 bool scaled = false;
                 for (int64_t r = L.row_off[i]; r < L.row_off[i + 1]; ++r) {
@@ -747,7 +851,8 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
                         scaled = true;
                 }
                 const int32_t n = L.ns[i];
-                if (!scaled && n <= 64) {
+                nmax = std::max(nmax, n);
+                if (!scaled) {
                     cls[i] = 0;
                     ash_off_s[i] = ash_words;
                     ash_words += int64_t(n) * n;
@@ -760,28 +865,31 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
                     vbrow[i] = vmode[i] ? 0 : r;
                     wofs[i] = wrows;
                     wrows += int64_t(vK[i]) * n;
-                    nmax_vec = std::max(nmax_vec, n);
+                    kmax = std::max(kmax, vK[i]);
                     vec.push_back(int32_t(i));
                 }
             }
             h->n_mf = int64_t(mf.size());
             h->n_vec = int64_t(vec.size());
-            h->nmax_vec = nmax_vec;
+            // rows per wave of the local update: n_s <= 4 RPW
+            if (nmax > 128) fail(LDOPF_UNSUPPORTED, "the batched path takes subsystems of at most 128 variables");
+            h->nmax = nmax;
+            h->kmax = kmax;
+            h->rpw = nmax <= 40 ? 10 : (nmax <= 64 ? 16 : 32);
             {
-                const size_t vec_lds = size_t(3 * nmax_vec * 64) * 4;
-                if (vec_lds > 163840) fail(LDOPF_UNSUPPORTED, "a voltage-dependent subsystem is too large for the batched path");
-                if (vec_lds > 65536)
-                    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_local_vec_kernel),
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(vec_lds)),
-                              "vector kernel LDS");
+                const size_t lds = local_lds(*h);
+                if (lds > 65536)
+                    hip_check(hipFuncSetAttribute(local_kernel(h->rpw), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)),
+                              "local update LDS");
             }
             const int32_t Bp = h->Bp;
+            // the local update indexes the global x with 32-bit offsets
+            if (int64_t(L.n) * Bp >= (int64_t(1) << 31)) fail(LDOPF_UNSUPPORTED, "n x padded scenarios exceeds 2^31");
             h->BB.alloc(size_t(nloc) * Bp, "scenario bbar");
             h->W.alloc(size_t(std::max<int64_t>(wrows, 1)) * Bp, "scenario operators");
-            cls_d.upload(cls, s, "upload classes");
+            h->cls.upload(cls, s, "upload classes");
             h->vK.upload(vK, s, "upload classes");
             vbrow_d.upload(vbrow, s, "upload classes");
-            h->vmode.upload(vmode, s, "upload classes");
             h->wofs.upload(wofs, s, "upload classes");
             flag_d.alloc(1, "flag");
             hip_check(hipMemsetAsync(flag_d.p, 0, 4, s), "flag");
@@ -836,7 +944,7 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
                 pk.loc_off = h->loc_off.p;
                 pk.basis_off = basis_off.p;
                 pk.rank = rank_d.p;
-                pk.cls = cls_d.p;
+                pk.cls = h->cls.p;
                 pk.vK = h->vK.p;
                 pk.vbrow = vbrow_d.p;
                 pk.wofs = h->wofs.p;
@@ -864,18 +972,15 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             std::vector<double> abar_h(words);
             hip_check(hipMemcpy(abar_h.data(), abar.p, words * 8, hipMemcpyDeviceToHost), "download abar");
             std::vector<float> ash(std::max<int64_t>(ash_words, 1));
-            std::vector<int64_t> ash_off;
             for (int32_t i : mf) {
                 const int64_t nn = int64_t(L.ns[i]) * L.ns[i];
                 for (int64_t t = 0; t < nn; ++t) ash[ash_off_s[i] + t] = float(abar_h[boff[i] + t]);
-                ash_off.push_back(ash_off_s[i]);
             }
             h->ash.upload(ash, s, "upload shared operators");
-            h->ash_off.upload(ash_off.empty() ? std::vector<int64_t>{0} : ash_off, s, "upload shared operators");
-            h->mf_h = mf;
-            h->vec_h = vec;
-            h->mf_sub.upload(mf.empty() ? std::vector<int32_t>{0} : mf, s, "upload classes");
-            h->vec_sub.upload(vec.empty() ? std::vector<int32_t>{0} : vec, s, "upload classes");
+            std::vector<LocalMeta> meta(S);
+            for (int64_t i = 0; i < S; ++i)
+                meta[i] = LocalMeta{L.ns[i], cls[i], vK[i], vmode[i], L.loc_off[i], cls[i] ? wofs[i] : ash_off_s[i]};
+            h->meta.upload(meta, s, "upload subsystems");
 
             // consensus structure: copies of each variable, global data in FP32
             std::vector<int32_t> g32(nloc), var_off(L.n + 1, 0), var_copy(nloc);
@@ -896,6 +1001,13 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             h->gidx.upload(g32, s, "upload gidx");
             h->var_off.upload(var_off, s, "upload copies");
             h->var_copy.upload(var_copy, s, "upload copies");
+            std::vector<int4> ell(L.n);
+            for (int64_t v = 0; v < L.n; ++v) {
+                int32_t e[4] = {-1, -1, -1, -1};
+                for (int32_t i = 0; i < 4 && var_off[v] + i < var_off[v + 1]; ++i) e[i] = var_copy[var_off[v] + i];
+                ell[v] = int4{e[0], e[1], e[2], e[3]};
+            }
+            h->ell.upload(ell, s, "upload copies");
             h->crho.upload(crho, s, "upload c");
             h->lo.upload(lo, s, "upload lo");
             h->hi.upload(hi, s, "upload hi");
@@ -910,8 +1022,8 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             h->iters.alloc(Bp, "iterations");
             h->res.alloc(size_t(Bp) * 4, "residuals");
             h->ctrl.alloc(4, "control");
-            const int32_t rows = o.rows_per_part > 0 ? o.rows_per_part : 256;
-            set_chunks(*h, mf, vec, rows, 1024);
+            const int32_t rows = o.rows_per_part > 0 ? o.rows_per_part : 64;
+            set_chunks(*h, rows, 256);
             batch_reset(*h);
         } catch (...) {
             delete h;
@@ -1028,29 +1140,34 @@ int ldopf_batch_get_sizes(const ldopf_batch* h, ldopf_batch_sizes* o) {
         o->scenario_operator_words = int64_t(h->W.count);
         o->shared_operator_words = int64_t(h->ash.count);
         o->rows_per_chunk = h->rows_per_chunk;
-        o->waves_per_tile = std::max(h->mf_grid, h->vec_grid);
+        o->blocks_per_tile = h->grid;
         o->graph_sweeps = h->graph_sweeps;
     });
 }
 
-int ldopf_batch_tune(ldopf_batch* h, const char* cache_path, int32_t* rows_per_chunk, int32_t* waves_per_tile) {
+int ldopf_batch_tune(ldopf_batch* h, const char* cache_path, int32_t* rows_per_chunk, int32_t* blocks_per_tile) {
     return guard([&] {
         need(h, "handle");
         std::string path;
         if (cache_path) path = cache_path;
         const std::string key = tune_key(*h);
-        const std::vector<int32_t> mf = h->mf_h, vec = h->vec_h;
-        int32_t best_r = h->rows_per_chunk, best_w = std::max(h->mf_grid, h->vec_grid);
+        int32_t best_r = h->rows_per_chunk, best_w = h->grid;
         if (path.empty() || !read_tune_cache(path, key, &best_r, &best_w)) {
             // time a short fixed number of sweeps for each candidate
             const int64_t keep_iter = h->opts.max_iter;
             const int32_t keep_check = h->opts.check_termination;
-            h->opts.max_iter = 2 * h->graph_sweeps;
             h->opts.check_termination = 0;
             double best = 1e300;
-            for (int32_t r : {64, 128, 256, 512})
-                for (int32_t w : {256, 1024, 4096}) {
-                    set_chunks(*h, mf, vec, r, w);
+            for (int32_t r : {32, 64, 128, 256})
+                for (int32_t w : {64, 128, 256, 512}) {
+                    set_chunks(*h, r, w);
+                    // one untimed graph to warm up, then four timed ones
+                    h->opts.max_iter = h->graph_sweeps;
+                    drop_graph(*h);
+                    batch_reset(*h);
+                    run_to_done(*h, nullptr);
+                    h->opts.max_iter = 4 * h->graph_sweeps;
+                    drop_graph(*h);
                     batch_reset(*h);
                     double ms = 0.0;
                     run_to_done(*h, &ms);
@@ -1062,12 +1179,13 @@ int ldopf_batch_tune(ldopf_batch* h, const char* cache_path, int32_t* rows_per_c
                 }
             h->opts.max_iter = keep_iter;
             h->opts.check_termination = keep_check;
+            drop_graph(*h);
             if (!path.empty()) write_tune_cache(path, key, best_r, best_w);
         }
-        set_chunks(*h, mf, vec, best_r, best_w);
+        set_chunks(*h, best_r, best_w);
         batch_reset(*h);
         if (rows_per_chunk) *rows_per_chunk = best_r;
-        if (waves_per_tile) *waves_per_tile = best_w;
+        if (blocks_per_tile) *blocks_per_tile = h->grid;
     });
 }
 
@@ -1079,14 +1197,7 @@ int ldopf_batch_set_options(ldopf_batch* h, const ldopf_options* opts) {
         if (opts->precision != h->opts.precision) fail(LDOPF_INVALID_ARGUMENT, "precision is fixed at creation");
         if (opts->rho != h->opts.rho) fail(LDOPF_INVALID_ARGUMENT, "rho is fixed at creation for a batch");
         h->opts = *opts;
-        if (h->exec) {
-            (void)hipGraphExecDestroy(h->exec);
-            h->exec = nullptr;
-        }
-        if (h->graph) {
-            (void)hipGraphDestroy(h->graph);
-            h->graph = nullptr;
-        }
+        drop_graph(*h);
     });
 }
 

@@ -28,18 +28,17 @@ struct PrecomputeArgs {
     double tol_rhs; // ... and then its right-hand side must be below tol_rhs * (1 + max |b_s|)
 };
 
-// Grid barrier words: [0] top arrival counter, [64] generation, then one
-// counter per group of kBarGroup workgroups at kBarGroupBase + 64 * group.
-constexpr unsigned kBarGroup = 16;
-constexpr unsigned kBarGroupBase = 128;
-constexpr int kBarWords = 16384;
-constexpr int kMaxParts = int((kBarWords - kBarGroupBase) / 64) * int(kBarGroup);
+// Residual sums of every part for the last kRing sweeps: [kRing][P][8]
+// doubles; a part's word is emptied once every part has read it.
+constexpr int kRing = 8;
+// Parts the sweep can run: the reader wave of the test holds four parts per lane.
+constexpr int kMaxParts = 256;
 
 struct SweepStatus {
     int64_t iters;     // sweep whose state is returned
     int64_t computed;  // sweeps computed (the test of a sweep is read during the next one)
     int32_t converged;
-    int32_t flags;  // 1: barrier wait timed out, 2: non-finite residuals
+    int32_t flags;  // 1: an exchange wait timed out, 2: non-finite residuals
     double pres, dres, eps_p, eps_d;
 };
 
@@ -67,9 +66,8 @@ struct SweepArgs {
     double* xs;          // state in and out, canonical copy order
     double* lam;
     double* x;           // global x out
-    T* bpart;            // [2][n_slots] boundary partial sums
-    double* rpart;       // [2][P][8] residual partial sums
-    unsigned* bar;       // [0] arrivals, [64] generation
+    T* bpart;            // [2][n_slots] boundary partial sums, one word per (var, writer, reader)
+    double* rpart;       // [kRing][P][8] residual partial sums
     double* hist;        // [hist_cap][4]
     int64_t hist_cap;
     SweepStatus* st;
@@ -79,7 +77,7 @@ struct SweepArgs {
     int64_t n_slots;
     int32_t check;
     int32_t P;
-    uint64_t spin_limit; // wall-clock ticks a barrier may wait
+    uint64_t spin_limit; // wall-clock ticks an exchange wait may take
     double* prof;        // nullable: per-phase wall-clock ticks of workgroup 0 (8 entries)
 };
 

@@ -16,8 +16,11 @@
 //    solve. One iteration: global update closed_1 for the variables the
 //    workgroup touches, local update closed_2 in rank form, dual update
 //    ADMM-3, residual partial sums in FP64, publication of the boundary
-//    partial sums, one grid barrier, and the termination test of Section
-//    III-C evaluated identically by every workgroup.
+//    partial sums to the neighbouring workgroups, and the termination test
+//    of Section III-C evaluated identically by every workgroup. There is no
+//    grid barrier: a workgroup waits only for the exchange words it reads
+//    (boundary partial sums of its neighbours, every part's residual sums
+//    of the previous sweep).
 //
 // The local update in rank form: with W the K_s rows of the smaller of the
 // row-space basis (mode 1) and the complement basis (mode 0),
@@ -27,6 +30,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -90,14 +94,6 @@ __device__ inline void st_agent(float* p, float v) {
     __hip_atomic_store(reinterpret_cast<unsigned int*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline double ld_agent(const double* p) {
-    return __longlong_as_double((long long)__hip_atomic_load(
-        reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-__device__ inline float ld_agent(const float* p) {
-    return __uint_as_float(__hip_atomic_load(reinterpret_cast<unsigned int*>(const_cast<float*>(p)), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT));
-}
 
 }  // namespace
 
@@ -135,52 +131,50 @@ struct SubLds {
 };
 static_assert(sizeof(SubLds) == 16, "SubLds layout");
 
-// Grid-wide barrier over the co-resident workgroups of a cooperative launch.
-// Arrivals are split over groups of kBarGroup workgroups, each with its own
-// counter on its own cache line, so that no more than kBarGroup atomics hit
-// one address per barrier; the last arriver of a group arrives at the top
-// counter, and the last arriver there publishes the new generation. Every
-// wait is bounded by a wall-clock limit so that a broken launch ends instead
-// of hanging; the caller sees the failure in the return value.
-__device__ inline bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& epoch, uint64_t limit, int* ok_lds) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        ++epoch;
-        int ok = 1;
-        if (nblocks > 1) {
-            const unsigned g = blockIdx.x / kBarGroup;
-            const unsigned ngroups = (nblocks + kBarGroup - 1) / kBarGroup;
-            const unsigned gsize = min(kBarGroup, nblocks - g * kBarGroup);
-            unsigned* top = bar;
-            unsigned* gen = bar + 64;
-            unsigned* gc = bar + kBarGroupBase + 64 * g;
-            bool released = false;
-            const unsigned prev = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev == gsize - 1) {
-                __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned p2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-                if (p2 == ngroups - 1) {
-                    __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    released = true;
-                }
-            }
-            if (!released) {
-                const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (wall_clock64() - t0 > limit) {
-                        ok = 0;
-                        break;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
+// Exchange words between workgroups. An empty word holds a signalling-NaN
+// bit pattern: arithmetic only ever returns quiet NaNs, so a computed value
+// never looks empty. A reader polls a word until it is not empty.
+template <typename T>
+struct Word;
+template <>
+struct Word<double> {
+    using U = unsigned long long;
+    static constexpr U kEmpty = 0x7FF4A5A5A5A5A5A5ull;
+    __device__ static double value(U u) { return __longlong_as_double((long long)u); }
+};
+template <>
+struct Word<float> {
+    using U = unsigned int;
+    static constexpr U kEmpty = 0x7FA5A5A5u;
+    __device__ static float value(U u) { return __uint_as_float(u); }
+};
+
+template <typename T>
+__device__ inline typename Word<T>::U ld_word(const T* p) {
+    using U = typename Word<T>::U;
+    return __hip_atomic_load(reinterpret_cast<U*>(const_cast<T*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void st_empty(T* p) {
+    using U = typename Word<T>::U;
+    __hip_atomic_store(reinterpret_cast<U*>(p), Word<T>::kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Re-read an exchange word until it is written; a wait longer than `limit`
+// wall-clock ticks clears *ok (a broken launch then ends instead of hanging).
+template <typename T>
+__device__ inline T await_word(const T* p, typename Word<T>::U u, uint64_t limit, int* ok) {
+    if (u != Word<T>::kEmpty) return Word<T>::value(u);
+    const uint64_t t0 = wall_clock64();
+    while (u == Word<T>::kEmpty) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > limit) {
+            *ok = 0;
+            return T(0);
         }
-        *ok_lds = ok;
+        u = ld_word(p);
     }
-    __syncthreads();
-    return *ok_lds != 0;
+    return Word<T>::value(u);
 }
 
 // Lanes per (subsystem, basis row) task of t = W v: as many as the
@@ -196,7 +190,7 @@ __device__ inline int task_lanes(int tasks, int threads) {
 template <typename T, bool PROF>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int bar_ok;
+    __shared__ int ok_lds;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const PartInfo pi = a.parts[blockIdx.x];
     const LdsLayout L = lds_layout(sizeof(T), uint32_t(pi.w_words), uint32_t(pi.n_row), uint32_t(pi.n_tk),
@@ -213,9 +207,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     T* vlo = reinterpret_cast<T*>(smem + L.lo);
     T* vhi = reinterpret_cast<T*>(smem + L.hi);
     T* vcnt = reinterpret_cast<T*>(smem + L.cnt);
-    int32_t* slo = reinterpret_cast<int32_t*>(smem + L.slot_lo);
-    int32_t* shi = reinterpret_cast<int32_t*>(smem + L.slot_hi);
-    int32_t* sown = reinterpret_cast<int32_t*>(smem + L.slot_own);
+    int32_t* sbase = reinterpret_cast<int32_t*>(smem + L.slot_lo);
+    int32_t* sm_ = reinterpret_cast<int32_t*>(smem + L.slot_hi);
+    int32_t* sme = reinterpret_cast<int32_t*>(smem + L.slot_own);
     uint16_t* rlv = reinterpret_cast<uint16_t*>(smem + L.row_lvar);
     uint16_t* rsub = reinterpret_cast<uint16_t*>(smem + L.row_sub);
     uint16_t* coff = reinterpret_cast<uint16_t*>(smem + L.copy_off);
@@ -230,8 +224,10 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     const int R = pi.n_row, V = pi.n_var, TK = pi.n_tk;
     const unsigned P = unsigned(a.P);
     const int64_t ns = a.n_slots;
+    const uint64_t limit = a.spin_limit;
 
     // ---- load this part into LDS
+    if (tid == 0) ok_lds = 1;
     for (int i = tid; i < pi.n_sub; i += nt) {
         const SubMeta m = a.subs[pi.sub_begin + i];
         meta[i] = SubLds{m.row0, m.n, m.k, m.t0, m.mode, m.w0, 0u};
@@ -252,9 +248,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         vlo[v] = T(a.lo[g]);
         vhi[v] = T(a.hi[g]);
         vcnt[v] = T(1.0 / a.cnt[g]);  // reciprocal of the copy count N_i
-        slo[v] = a.var_slot_lo[pi.var_begin + v];
-        shi[v] = a.var_slot_hi[pi.var_begin + v];
-        sown[v] = a.var_slot[pi.var_begin + v];
+        sbase[v] = a.var_slot_lo[pi.var_begin + v];
+        sm_[v] = a.var_slot_hi[pi.var_begin + v];
+        sme[v] = a.var_slot[pi.var_begin + v];
     }
     for (int q = tid; q < TK; q += nt) tks[q] = a.tk_sub[pi.tk_begin + q];
     for (int i = wv; i < pi.n_sub; i += nw) {
@@ -267,36 +263,76 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     }
     __syncthreads();
 
+    // The last wave reads the residual sums of all parts back and runs the
+    // test; it takes no part in the global update and the boundary exchange,
+    // whose loads would otherwise wait (in-order vmcnt) on its loads in
+    // flight. With a single wave, that wave does everything.
+    const int tw = nw - 1;
+    const int g_threads = nw > 1 ? nt - 64 : nt;
+
+    // publish a boundary variable's partial sum to every other owner
+    auto publish = [&](T* buf, int v, T acc) {
+        const int sb = sbase[v];
+        if (sb < 0) return;
+        const int m = sm_[v], me = sme[v];
+        for (int j = 0; j < m; ++j)
+            if (j != me) st_agent(buf + sb + j * m + me, acc);
+    };
+    // all owners' partial sums in owner order: the m - 1 foreign ones read
+    // (up to four loads in flight), waited for, and their words emptied
+    auto gather = [&](T* buf, int v) -> T {
+        const int sb = sbase[v], m = sm_[v], me = sme[v];
+        const int f = m - 1;
+        const T* rd = buf + sb + me * m;
+        typename Word<T>::U u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = k < f ? ld_word(rd + (k < me ? k : k + 1)) : Word<T>::kEmpty;
+        T w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = k < f ? await_word(rd + (k < me ? k : k + 1), u[k], limit, &ok_lds) : T(0);
+        T s = T(0);
+        for (int i = 0; i < m; ++i) {
+            T val;
+            if (i == me) {
+                val = ownp[v];
+            } else {
+                const int k = i < me ? i : i - 1;
+                if (k < 4) {
+                    val = k == 0 ? w[0] : (k == 1 ? w[1] : (k == 2 ? w[2] : w[3]));
+                } else {
+                    val = await_word(rd + i, ld_word(rd + i), limit, &ok_lds);
+                }
+                st_empty(buf + sb + me * m + i);
+            }
+            s = i == 0 ? val : s + val;
+        }
+        return s;
+    };
+
     // ---- partial sums of the starting state for the first global update
-    for (int v = tid; v < V; v += nt) {
+    for (int v = tid; tid < g_threads && v < V; v += g_threads) {
         T acc = T(0);
         for (int q = coff[v]; q < coff[v + 1]; ++q) {
             const int r = crow[q];
             acc += xs[0][r] - lam[0][r] * irho;
         }
         ownp[v] = acc;
-        if (sown[v] >= 0) st_agent(a.bpart + sown[v], acc);
+        publish(a.bpart, v, acc);
     }
-    // every wave's device-scope stores are complete before its workgroup arrives
-    __builtin_amdgcn_s_waitcnt(0);
-    unsigned epoch = 0;
-    bool ok = grid_barrier(a.bar, P, epoch, a.spin_limit, &bar_ok);
+    __syncthreads();
 
     const int GA = task_lanes(TK, nt);
-    // The last wave reads the grid-wide residual sums back and runs the test;
-    // it takes no part in the global update, whose boundary-slot loads would
-    // otherwise wait (in-order vmcnt) on the read-back loads in flight.
-    const int tw = nw - 1;
-    const int g_threads = nw > 1 ? nt - 64 : nt;
-    // residual partial sums of the previous sweep, loaded one sweep ahead of
-    // their use (wave tw, lane l holds the parts l, l + 64, l + 128, l + 192)
-    double pv[4][5];
-    auto issue_partials = [&](int par) {
+    // residual sums of all parts for one sweep, as raw words (wave tw, lane l
+    // holds the parts l, l + 64, l + 128, l + 192)
+    unsigned long long pv[4][5];
+    auto ring = [&](int64_t sweep) -> double* { return a.rpart + int64_t(sweep & (kRing - 1)) * P * 8; };
+    auto issue_ring = [&](int64_t sweep) {
+        const double* base = ring(sweep);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const unsigned p = unsigned(lane) + 64u * u;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) pv[u][q] = p < P ? ld_agent(a.rpart + (int64_t(par) * P + p) * 8 + q) : 0.0;
+            for (int q = 0; q < 5; ++q) pv[u][q] = p < P ? ld_word(base + p * 8 + q) : 0ull;
         }
     };
     uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -313,24 +349,36 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     int64_t done = 0;     // sweeps computed
     int64_t result = 0;   // sweep whose state is returned
     int converged = 0, nonfinite = 0;
+    bool ok = true;
     double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double sq = sqrt(double(a.nloc));
-    // termination test of one finished sweep from the grid-wide sums held in pv
+    // termination test of one finished sweep from every part's sums (loads
+    // issued by issue_ring); identical on every workgroup
     auto decide = [&](int64_t sweep) -> bool {
         if (wv == tw) {
+            const double* base = ring(sweep);
+            double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const unsigned p = unsigned(lane) + 64u * u;
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+                    if (p < P) acc[q] += await_word(base + p * 8 + q, pv[u][q], limit, &ok_lds);
+            }
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                const double acc = wave_total(pv[0][q] + pv[1][q] + pv[2][q] + pv[3][q]);
-                if (lane == 0) tot[q] = acc;
+                const double t = wave_total(acc[q]);
+                if (lane == 0) tot[q] = t;
             }
         }
         __syncthreads();
+        ok = ok_lds != 0;
 #pragma unroll
         for (int q = 0; q < 5; ++q) d[q] = tot[q];
         const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
         const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
         const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
-        if (blockIdx.x == 0 && tid == 0 && sweep <= a.hist_cap) {
+        if (ok && blockIdx.x == 0 && tid == 0 && sweep <= a.hist_cap) {
             double* h = a.hist + (sweep - 1) * 4;
             h[0] = pres;
             h[1] = dres;
@@ -343,40 +391,35 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     };
 
     bool stopped = false;
-    while (ok && done < a.max_iter) {
+    while (done < a.max_iter) {
         const int cur = int(done & 1), nx = cur ^ 1;
-        const T* bcur = a.bpart + int64_t(cur) * ns;
+        T* bcur = a.bpart + int64_t(cur) * ns;
         T* bnx = a.bpart + int64_t(nx) * ns;
         T* xg = xl[nx];
+        // wave tw's stores (ring words, emptied ring words) complete before
+        // it stores again; it waits here, off the critical path
+        if (wv == tw && nw > 1) __builtin_amdgcn_s_waitcnt(0);
         // closed_1: clipped average of the copies
         for (int v = tid; tid < g_threads && v < V; v += g_threads) {
-            T s;
-            if (slo[v] < 0) {
-                s = ownp[v];
-            } else {
-                // all owners' slots in owner order; loads issued together
-                const int q0 = slo[v], q1 = shi[v];
-                T b0 = ld_agent(bcur + q0);
-                T b1 = q0 + 1 < q1 ? ld_agent(bcur + q0 + 1) : T(0);
-                T b2 = q0 + 2 < q1 ? ld_agent(bcur + q0 + 2) : T(0);
-                T b3 = q0 + 3 < q1 ? ld_agent(bcur + q0 + 3) : T(0);
-                s = b0 + b1;
-                if (q0 + 2 < q1) s += b2;
-                if (q0 + 3 < q1) s += b3;
-                for (int q = q0 + 4; q < q1; ++q) s += ld_agent(bcur + q);
-            }
+            const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
             T xv = (s - crho[v]) * vcnt[v];
             xv = xv < vlo[v] ? vlo[v] : xv;
             xv = xv > vhi[v] ? vhi[v] : xv;
             xg[v] = xv;
         }
         __syncthreads();
+        if (ok_lds == 0) {
+            ok = false;
+            break;
+        }
         stamp(0);
         // v = B_s x + lambda_s / rho
         const T* lc = lam[cur];
         for (int r = tid; r < R; r += nt) vb[r] = xg[rlv[r]] + lc[r] * irho;
         __syncthreads();
         stamp(1);
+        // the previous sweep's residual sums of every part, read during this one
+        if (wv == tw && done >= 1) issue_ring(done);
         // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
         for (int base = 0; base < TK * GA; base += nt) {
             const int q0 = base + tid;
@@ -444,42 +487,49 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             red[wv * 8 + 3] = p3;
             red[wv * 8 + 4] = p4;
         }
+        // this sweep's emptied exchange words are stored before any partial
+        // sum of this sweep is published
+        if (wv != tw || nw == 1) __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         stamp(3);
         // partial sums for the next global update; publish boundary slots
-        for (int v = tid; v < V; v += nt) {
+        for (int v = tid; tid < g_threads && v < V; v += g_threads) {
             T acc = T(0);
             for (int q = coff[v]; q < coff[v + 1]; ++q) {
                 const int r = crow[q];
                 acc += xn[r] - ln[r] * irho;
             }
             ownp[v] = acc;
-            if (sown[v] >= 0) st_agent(bnx + sown[v], acc);
+            publish(bnx, v, acc);
         }
-        if (tid < 5) {
+        if (wv == tw && lane < 5) {
             double acc = 0.0;
-            for (int w = 0; w < nw; ++w) acc += red[w * 8 + tid];
-            st_agent(a.rpart + (int64_t(nx) * P + blockIdx.x) * 8 + tid, acc);
+            for (int w = 0; w < nw; ++w) acc += red[w * 8 + lane];
+            st_agent(ring(done + 1) + blockIdx.x * 8 + lane, acc);
         }
-        __builtin_amdgcn_s_waitcnt(0);
         stamp(4);
-        ok = grid_barrier(a.bar, P, epoch, a.spin_limit, &bar_ok);
-        stamp(5);
-        if (!ok) break;
         ++done;
-        // the test of the previous sweep, from sums loaded during this one
-        if (done >= 2 && decide(done - 1)) {
-            result = done - 1;
-            stopped = true;
-            break;
+        // the test of the previous sweep, from sums read during this one
+        if (done >= 2) {
+            const bool stop = decide(done - 1);
+            if (!ok) break;
+            if (stop) {
+                result = done - 1;
+                stopped = true;
+                break;
+            }
+            // every part has read the ring words of sweep done - 3
+            if (wv == tw && lane < 5 && done >= 4) st_empty(ring(done - 3) + blockIdx.x * 8 + lane);
         }
-        if (wv == tw) issue_partials(int(done & 1));
-        stamp(6);
+        stamp(5);
     }
     if (ok && !stopped) {
-        // the last computed sweep (max_iter reached): its sums are in flight
+        // the last computed sweep (max_iter reached)
         result = done;
-        if (done > 0) decide(done);
+        if (done > 0) {
+            if (wv == tw) issue_ring(done);
+            decide(done);
+        }
     }
     // ---- write the state of sweep `result` back (canonical order, FP64)
     const int fp = int(result & 1);
@@ -505,10 +555,16 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     }
 }
 
-__global__ void reset_sync_kernel(unsigned* bar, int words, SweepStatus* st) {
-    // plain stores; runs on the same stream before every sweep launch
-    for (int t = threadIdx.x; t < words; t += blockDim.x) bar[t] = 0u;
-    if (threadIdx.x == 0) {
+// Before every sweep launch, on the same stream: every exchange word empty,
+// the status cleared (plain stores).
+template <typename T>
+__global__ void reset_sync_kernel(T* bpart, int64_t n_bwords, double* rpart, int64_t n_rwords, SweepStatus* st) {
+    const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x, stride = int64_t(gridDim.x) * blockDim.x;
+    using UB = typename Word<T>::U;
+    using UR = typename Word<double>::U;
+    for (int64_t i = i0; i < n_bwords; i += stride) reinterpret_cast<UB*>(bpart)[i] = Word<T>::kEmpty;
+    for (int64_t i = i0; i < n_rwords; i += stride) reinterpret_cast<UR*>(rpart)[i] = Word<double>::kEmpty;
+    if (i0 == 0) {
         st->iters = 0;
         st->computed = 0;
         st->converged = 0;
@@ -547,7 +603,9 @@ hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_p
 
 template <typename T>
 static hipError_t launch_sweep_t(const SweepArgs<T>& a, int grid, int block, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL(reset_sync_kernel, dim3(1), dim3(256), 0, stream, a.bar, kBarWords, a.st);
+    const int64_t nb = 2 * std::max<int64_t>(a.n_slots, 1), nr = int64_t(kRing) * a.P * 8;
+    const unsigned rgrid = unsigned(std::min<int64_t>(256, (std::max(nb, nr) + 255) / 256));
+    hipLaunchKernelGGL(reset_sync_kernel<T>, dim3(rgrid), dim3(256), 0, stream, a.bpart, nb, a.rpart, nr, a.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     SweepArgs<T> copy = a;

@@ -88,14 +88,14 @@ struct Plan {
     std::vector<uint16_t> row_lvar;    // part-local var of each device row
     std::vector<uint16_t> row_sub;     // part-local subsystem of each device row
     std::vector<int32_t> var_gid;      // global id of each part-local var
-    std::vector<int32_t> var_slot;     // own boundary slot or -1 for an interior var
-    std::vector<int32_t> var_slot_lo;  // first slot of the var (all owners, in part order)
-    std::vector<int32_t> var_slot_hi;
+    std::vector<int32_t> var_slot;     // boundary var: this part's owner index; -1 interior
+    std::vector<int32_t> var_slot_lo;  // boundary var: slot base (m^2 slots, reader-major); -1 interior
+    std::vector<int32_t> var_slot_hi;  // boundary var: number of owner parts m
     std::vector<uint8_t> var_writer;   // 1 if this part writes the var to the output x
     std::vector<uint16_t> var_copy_off;  // per part: n_var + 1 offsets into var_copy_rows
     std::vector<uint16_t> var_copy_rows; // part-local rows holding a copy, grouped by var
     std::vector<uint16_t> tk_sub;      // part-local subsystem of each (s, k) task
-    int32_t n_slots = 0;               // boundary (var, owner part) pairs
+    int32_t n_slots = 0;               // boundary (var, writer part, reader part) slots
     int64_t rank_words = 0;
 };
 

@@ -4,11 +4,12 @@
 // depth-first walk of the feeder), one run per workgroup. Each workgroup
 // keeps its run's operators and state in LDS for the whole solve. A global
 // variable whose copies all sit in one run is interior: its clipped average
-// (closed_1) is computed inside that workgroup. A variable shared by several
-// runs is a boundary variable: every owner publishes its partial sum of
-// (x_k - lambda_k / rho) into one slot per owner, and after the grid barrier
-// each owner adds the slots in owner order, so all owners compute the same
-// value bit for bit.
+// (closed_1) is computed inside that workgroup. A variable shared by m runs
+// is a boundary variable: every owner sends its partial sum of
+// (x_k - lambda_k / rho) to each other owner through a slot of its own for
+// that (writer, reader) pair, m^2 slots per variable with the reader's block
+// of m first (slot base + reader * m + writer); each owner adds the m partial
+// sums in owner order, so all owners compute the same value bit for bit.
 
 #include <algorithm>
 #include <cmath>
@@ -166,15 +167,16 @@ Plan make_plan(const ConsensusLP& lp, const std::vector<int32_t>& rank, bool fp3
             P = std::min<int32_t>(cap, std::max<int32_t>(P + 1, int32_t(std::ceil(P * 1.15))));
             continue;
         }
-        // boundary slots: one per (shared variable, owner part), owners in part order
+        // boundary slots: owner_count^2 per shared variable, owners in part order
         std::vector<int32_t> slot_lo(lp.n, -1), seen(lp.n, 0);
-        int32_t slots = 0;
+        int64_t slots = 0;
         for (int64_t g = 0; g < lp.n; ++g)
             if (owner_count[g] > 1) {
-                slot_lo[g] = slots;
-                slots += owner_count[g];
+                slot_lo[g] = int32_t(slots);
+                slots += int64_t(owner_count[g]) * owner_count[g];
+                if (slots >= (int64_t(1) << 30)) fail(LDOPF_UNSUPPORTED, "too many boundary slots");
             }
-        pl.n_slots = slots;
+        pl.n_slots = int32_t(slots);
         const size_t nvar_total = pl.var_gid.size();
         pl.var_slot.assign(nvar_total, -1);
         pl.var_slot_lo.assign(nvar_total, -1);
@@ -188,9 +190,9 @@ Plan make_plan(const ConsensusLP& lp, const std::vector<int32_t>& rank, bool fp3
                 const int32_t my = seen[g]++;
                 pl.var_writer[q] = my == 0;
                 if (owner_count[g] > 1) {
-                    pl.var_slot[q] = slot_lo[g] + my;
-                    pl.var_slot_lo[q] = slot_lo[g];
-                    pl.var_slot_hi[q] = slot_lo[g] + owner_count[g];
+                    pl.var_slot[q] = my;                // this part's owner index
+                    pl.var_slot_lo[q] = slot_lo[g];     // slot base
+                    pl.var_slot_hi[q] = owner_count[g]; // owners m
                 }
             }
         }

@@ -47,7 +47,6 @@ struct ldopf_problem {
     DevBuf<uint16_t> row_lvar, row_sub, var_copy_off, var_copy_rows, tk_sub;
     DevBuf<uint8_t> var_writer;
     DevBuf<unsigned char> bpart;
-    DevBuf<unsigned> bar;
     DevBuf<SweepStatus> st;
 
     ~ldopf_problem() {

@@ -46,7 +46,7 @@ def test_batch_converged_matches_oracle(gpu, name):
     P = gpu
     net = feeder(name)
     f = _factors(net, 6, 1000 + len(name))
-    b = P.ldopf_batch_create(net, f)
+    b = P.ldopf_batch_create(net, f, P.ldopf_default_options(precision=1, max_iter=40000))
     st = b.solve()
     assert st.n_converged == 6 and st.code == 0
     for k in range(6):
@@ -106,7 +106,7 @@ def test_batch_tuner_keeps_results(gpu, tmp_path):
     b = P.ldopf_batch_create(net, f, opts)
     cache = str(tmp_path / "tune.txt")
     r, w = b.tune(cache)
-    assert r in (64, 128, 256, 512) and w in (256, 1024, 4096)
+    assert r in (32, 64, 128, 256) and 1 <= w <= 512
     assert open(cache).read().strip()
     b.solve()
     for k in range(4):
