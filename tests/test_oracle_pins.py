@@ -169,6 +169,81 @@ def test_voltage_drop_rows_match_phasor_physics():
         np.testing.assert_allclose(lhs, _phasor_drop(R, X, p, q, ph), atol=1e-12)
 
 
+def _pi_line_state(eps, gi, bi, gj, bj, seed):
+    """Exact single-phase AC state of a pi-model line i -> j with series
+    impedance eps (r + jx), shunt admittances gi + j bi at i and gj + j bj at j,
+    V_i = 1 and a unit series current: (w_i, w_j, p_ij, q_ij, p_ji, q_ji, |z|, |I|)."""
+    rng = np.random.default_rng(seed)
+    z = eps * complex(rng.uniform(0.2, 1.0), rng.uniform(0.2, 1.0))
+    Is = np.exp(1j * rng.uniform(0.0, 2 * math.pi))  # unit series current, any direction
+    Vi = 1.0 + 0.0j
+    Vj = Vi - z * Is
+    Sij = Vi * np.conj(Is + complex(gi, bi) * Vi)    # power entering the line at i
+    Sji = Vj * np.conj(-Is + complex(gj, bj) * Vj)   # power entering the line at j
+    return abs(Vi) ** 2, abs(Vj) ** 2, Sij.real, Sij.imag, Sji.real, Sji.imag, abs(z), abs(Is)
+
+
+def _line_row_residuals(net, state):
+    ix = model.build_index(net)
+    wi, wj, pij, qij, pji, qji = state[:6]
+    x = np.zeros(ix.n)
+    x[ix.w[(0, 0)]], x[ix.w[(1, 0)]] = wi, wj
+    x[ix.pij[(0, 0)]], x[ix.qij[(0, 0)]] = pij, qij
+    x[ix.pji[(0, 0)]], x[ix.qji[(0, 0)]] = pji, qji
+    return [sum(v * x[c] for c, v in row.items()) - rhs for row, rhs in model.line_rows(net, ix, 0)]
+
+
+def test_line_shunt_terms_match_pi_model_physics():
+    """Exact pi-model physics pins the shunt terms of powerloss-1, -2 and
+    voltage_mag_diff: as the series impedance eps z -> 0, the loss rows err by
+    the neglected series loss (O(eps)) and the drop row by |z I|^2 (O(eps^2));
+    a wrong sign or a missing shunt term would leave an O(shunt) error."""
+    gi, bi, gj, bj = 0.07, 0.11, 0.05, 0.09
+    net = dict(two_bus(r=1.0, x=1.0))
+    for key, val in (("line_gs_from", gi), ("line_bs_from", bi), ("line_gs_to", gj), ("line_bs_to", bj)):
+        arr = np.zeros((1, 3))
+        arr[0, 0] = val
+        net[key] = arr
+    for seed in range(5):
+        for eps in (1e-3, 1e-4):
+            st = _pi_line_state(eps, gi, bi, gj, bj, seed)
+            zabs, iabs = st[6], st[7]
+            # the oracle's rows use the line's r, x: give them this state's impedance
+            rng = np.random.default_rng(seed)
+            r, x = eps * rng.uniform(0.2, 1.0), eps * rng.uniform(0.2, 1.0)
+            net["line_r"] = np.array([[r] + [0.0] * 8])
+            net["line_x"] = np.array([[x] + [0.0] * 8])
+            loss_p, loss_q, drop = _line_row_residuals(net, st)
+            assert abs(loss_p) <= 1.01 * zabs * iabs ** 2
+            assert abs(loss_q) <= 1.01 * zabs * iabs ** 2
+            assert abs(drop) <= 1.01 * (zabs * iabs) ** 2
+            # a wrong shunt term would cost g or b in the loss rows and about
+            # 2 |z| g in the drop row, far above these bounds
+            assert min(gi, bi, gj, bj) > 20 * zabs * iabs ** 2
+            assert 2 * zabs * min(gi, bi) > 20 * (zabs * iabs) ** 2
+
+
+def test_mutation_flipped_line_shunt_sign_is_caught(monkeypatch):
+    """The physics pin fails for an oracle whose drop row adds g^s w_i."""
+    orig = model.line_rows
+
+    def flipped(net, ix, e):
+        rows = orig(net, ix, e)
+        gsi = net["line_gs_from"][e]
+        out = []
+        for k, (row, rhs) in enumerate(rows):
+            row = dict(row)
+            if k % 3 == 2:
+                Mp, _ = model.m_matrices(net["line_r"][e], net["line_x"][e])
+                row[ix.w[(int(net["line_from"][e]), 0)]] += 2 * Mp[0, 0] * gsi[0]
+            out.append((row, rhs))
+        return out
+
+    monkeypatch.setattr(model, "line_rows", flipped)
+    with pytest.raises(AssertionError):
+        test_line_shunt_terms_match_pi_model_physics()
+
+
 def test_delta_load_rows_match_balanced_delta_physics():
     """Bus injections of a delta load under nominal voltages satisfy VDLM-6..10."""
     net = make_feeder(FeederSpec(4, 1.0, 0.0, 2.4, "uniform100"), 1)
