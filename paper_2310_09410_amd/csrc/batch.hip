@@ -4,12 +4,15 @@
 // That scales the right-hand side of the load's model rows and, for a
 // voltage-dependent load (alpha or beta > 0), also the squared-voltage
 // coefficient of those rows (Section II-A, VDLM-1 and VDLM-2). So:
-//   * a subsystem with no voltage-dependent load has one operator Abar_s for
-//     all scenarios; its local update for B scenarios is Y = Bbar - Abar_s V
-//     with V of size n_s x B, a small GEMM, run on MFMA
-//     (v_mfma_f32_16x16x4f32, 64-scenario tiles);
+//   * a subsystem with no voltage-dependent load has one operator for all
+//     scenarios, kept in rank form (the K_s = min(r, n_s - r) orthonormal
+//     rows W of the smaller of the row-space and complement bases, so that
+//     -Abar_s v = v - W'(W v) or W'(W v)); its local update for B scenarios
+//     is two small GEMMs, T = W V and W'T with V of size n_s x B, run on
+//     MFMA (v_mfma_f32_16x16x4f32, 64-scenario tiles);
 //   * a subsystem with one has a different operator per scenario; its update
-//     runs in rank form per scenario (vector code, scenario-contiguous data).
+//     runs in the same rank form per scenario (vector code,
+//     scenario-contiguous data).
 // bbar differs per scenario everywhere. Operators are precomputed in FP64 on
 // the device for every (subsystem, scenario) pair and stored in FP32; the
 // sweep (global update, local update, dual update) runs in FP32; residual
@@ -254,8 +257,9 @@ __global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
 // the projection y, in LDS ([row][kZS], kZS = 80 floats: rows four apart fall on
 // disjoint halves of the 32 banks, so the MFMA operand reads do not
 // conflict).
-//   shared-operator class: Y = Bbar - Abar_s V on MFMA; wave w takes the
-//     16-row tiles w, w + 4, ... of Abar_s against the four 16-scenario tiles;
+//   shared-operator class: T = W V, then Y = Bbar + V - W'T (mode 1) or
+//     Bbar + W'T (mode 0), both on MFMA; wave w takes the 16-row tiles w,
+//     w + 4, ... of the product against the four 16-scenario tiles;
 //     v_mfma_f32_16x16x4f32 operand layout: lane l holds A[l % 16][l / 16],
 //     B[l / 16][l % 16] and D[4 (l / 16) + i][l % 16], i < 4;
 //   per-scenario class: t = W v (wave w takes basis rows w, w + 4, ...), then
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
     float* Vs = sm;                         // [nmax][kZS]
     float* Ys = Vs + a.nmax * kZS;          // [nmax][kZS]
     float* Ts = Ys + a.nmax * kZS;          // [kmax][kZS]
-    float* As = Ts + a.kmax * kZS;          // [nmax * nmax] shared operator
+    float* As = Ts + a.kmax * kZS;          // [kmax * nmax] shared rank-form rows
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int Bp = a.Bp;
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
             }
             if (m.cls == 0) {
                 const float* Ab = a.ash + m.off;
-                for (int i = tid; i < n * n; i += 256) As[i] = Ab[i];
+                for (int i = tid; i < m.K * n; i += 256) As[i] = Ab[i];
             }
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
@@ -321,7 +325,10 @@ __global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
             }
             __syncthreads();
             if (m.cls == 0) {
-                for (int mt = wv; mt * 16 < n; mt += 4) {
+                // T = W V: the K rows of W in 16-row tiles against the four
+                // 16-scenario tiles
+                const int K = m.K, mode = m.mode;
+                for (int mt = wv; mt * 16 < K; mt += 4) {
                     floatx4 acc[4];
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
                     for (int kk = 0; kk * 4 < n; ++kk) {
                         const int kc = kk * 4 + (lane >> 4);
                         const bool in = kc < n;
-                        const float av = (ar < n && in) ? As[ar * n + kc] : 0.f;
+                        const float av = (ar < K && in) ? As[ar * n + kc] : 0.f;
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
                             const float bv = in ? Vs[kc * kZS + nt * 16 + (lane & 15)] : 0.f;
@@ -341,7 +348,35 @@ __global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int row = mt * 16 + 4 * (lane >> 4) + i;
-                            if (row < n) Ys[row * kZS + nt * 16 + (lane & 15)] -= acc[nt][i];
+                            if (row < K) Ts[row * kZS + nt * 16 + (lane & 15)] = acc[nt][i];
+                        }
+                }
+                __syncthreads();
+                // U = W' T, then y = bbar + v - U (mode 1) or bbar + U (mode 0)
+                for (int mt = wv; mt * 16 < n; mt += 4) {
+                    floatx4 acc[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    const int ar = mt * 16 + (lane & 15);
+                    for (int kk = 0; kk * 4 < K; ++kk) {
+                        const int kc = kk * 4 + (lane >> 4);
+                        const bool in = kc < K;
+                        const float av = (ar < n && in) ? As[kc * n + ar] : 0.f;
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const float bv = in ? Ts[kc * kZS + nt * 16 + (lane & 15)] : 0.f;
+                            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[nt], 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int row = mt * 16 + 4 * (lane >> 4) + i;
+                            if (row < n) {
+                                const int e = row * kZS + nt * 16 + (lane & 15);
+                                Ys[e] = mode ? Ys[e] + (Vs[e] - acc[nt][i]) : Ys[e] + acc[nt][i];
+                            }
                         }
                 }
             } else {
@@ -605,7 +640,7 @@ BatchArgs batch_args(ldopf_batch& h) {
 }
 
 size_t local_lds(const ldopf_batch& h) {
-    return std::max<size_t>(size_t((2 * h.nmax + h.kmax) * kZS + h.nmax * h.nmax) * 4, size_t(4 * 5 * 64) * 8);
+    return std::max<size_t>(size_t((2 * h.nmax + h.kmax) * kZS + h.nmax * h.kmax) * 4, size_t(4 * 5 * 64) * 8);
 }
 
 const void* local_kernel(int rpw) {
@@ -852,20 +887,22 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
                 }
                 const int32_t n = L.ns[i];
                 nmax = std::max(nmax, n);
+                // rank form for both classes: the K = min(r, n - r) rows of the
+                // smaller of the row-space and complement bases
+                const int32_t r = rank[i];
+                vmode[i] = r <= n - r ? 1 : 0;
+                vK[i] = std::min(r, n - r);
+                vbrow[i] = vmode[i] ? 0 : r;
+                kmax = std::max(kmax, vK[i]);
                 if (!scaled) {
                     cls[i] = 0;
                     ash_off_s[i] = ash_words;
-                    ash_words += int64_t(n) * n;
+                    ash_words += int64_t(vK[i]) * n;
                     mf.push_back(int32_t(i));
                 } else {
                     cls[i] = 1;
-                    const int32_t r = rank[i];
-                    vmode[i] = r <= n - r ? 1 : 0;
-                    vK[i] = std::min(r, n - r);
-                    vbrow[i] = vmode[i] ? 0 : r;
                     wofs[i] = wrows;
                     wrows += int64_t(vK[i]) * n;
-                    kmax = std::max(kmax, vK[i]);
                     vec.push_back(int32_t(i));
                 }
             }
@@ -968,13 +1005,15 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             if (flag & 2) fail(LDOPF_INCONSISTENT_SUBSYSTEM, "a scaled subsystem has inconsistent rows");
             if (flag & 1) fail(LDOPF_UNSUPPORTED, "a subsystem's rank changes with the load scale");
 
-            // shared FP32 operators of the MFMA class
-            std::vector<double> abar_h(words);
-            hip_check(hipMemcpy(abar_h.data(), abar.p, words * 8, hipMemcpyDeviceToHost), "download abar");
+            // shared FP32 rank-form rows of the MFMA class, from the unit-scale basis
+            std::vector<double> basis_h(words);
+            hip_check(hipMemcpy(basis_h.data(), basis.p, words * 8, hipMemcpyDeviceToHost), "download basis");
             std::vector<float> ash(std::max<int64_t>(ash_words, 1));
             for (int32_t i : mf) {
-                const int64_t nn = int64_t(L.ns[i]) * L.ns[i];
-                for (int64_t t = 0; t < nn; ++t) ash[ash_off_s[i] + t] = float(abar_h[boff[i] + t]);
+                const int64_t n = L.ns[i];
+                for (int64_t k = 0; k < vK[i]; ++k)
+                    for (int64_t j = 0; j < n; ++j)
+                        ash[ash_off_s[i] + k * n + j] = float(basis_h[boff[i] + (vbrow[i] + k) * n + j]);
             }
             h->ash.upload(ash, s, "upload shared operators");
             std::vector<LocalMeta> meta(S);

@@ -28,8 +28,9 @@ struct PrecomputeArgs {
     double tol_rhs; // ... and then its right-hand side must be below tol_rhs * (1 + max |b_s|)
 };
 
-// Residual sums of every part for the last kRing sweeps: [kRing][P][8]
-// doubles; a part's word is emptied once every part has read it.
+// Residual sums of every part for the last kRing sweeps: [kRing][8][P]
+// doubles (quantity-major); a part's word is emptied once every part has
+// read it.
 constexpr int kRing = 8;
 // Parts the sweep can run: the reader wave of the test holds four parts per lane.
 constexpr int kMaxParts = 256;
@@ -67,7 +68,7 @@ struct SweepArgs {
     double* lam;
     double* x;           // global x out
     T* bpart;            // [2][n_slots] boundary partial sums, one word per (var, writer, reader)
-    double* rpart;       // [kRing][P][8] residual partial sums
+    double* rpart;       // [kRing][8][P] residual partial sums
     double* hist;        // [hist_cap][4]
     int64_t hist_cap;
     SweepStatus* st;

@@ -197,9 +197,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                                    uint32_t(pi.n_var), uint32_t(pi.n_sub), uint32_t(nw));
     T* W = reinterpret_cast<T*>(smem + L.W);
     T* bbar = reinterpret_cast<T*>(smem + L.bbar);
-    T* xs[2] = {reinterpret_cast<T*>(smem + L.xs0), reinterpret_cast<T*>(smem + L.xs1)};
-    T* lam[2] = {reinterpret_cast<T*>(smem + L.lam0), reinterpret_cast<T*>(smem + L.lam1)};
-    T* xl[2] = {reinterpret_cast<T*>(smem + L.xloc0), reinterpret_cast<T*>(smem + L.xloc1)};
+    T* xs[3] = {reinterpret_cast<T*>(smem + L.xs[0]), reinterpret_cast<T*>(smem + L.xs[1]),
+                reinterpret_cast<T*>(smem + L.xs[2])};
+    T* lam[3] = {reinterpret_cast<T*>(smem + L.lam[0]), reinterpret_cast<T*>(smem + L.lam[1]),
+                 reinterpret_cast<T*>(smem + L.lam[2])};
+    T* xl[3] = {reinterpret_cast<T*>(smem + L.xloc[0]), reinterpret_cast<T*>(smem + L.xloc[1]),
+                reinterpret_cast<T*>(smem + L.xloc[2])};
     T* vb = reinterpret_cast<T*>(smem + L.v);
     T* tb = reinterpret_cast<T*>(smem + L.t);
     T* ownp = reinterpret_cast<T*>(smem + L.ownp);
@@ -278,15 +281,30 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         for (int j = 0; j < m; ++j)
             if (j != me) st_agent(buf + sb + j * m + me, acc);
     };
-    // all owners' partial sums in owner order: the m - 1 foreign ones read
-    // (up to four loads in flight), waited for, and their words emptied
-    auto gather = [&](T* buf, int v) -> T {
+    // the words addressed to this part for a boundary variable (up to four
+    // loads in flight); a thread loads those of its first variable right
+    // after publishing, so that they travel while the test runs
+    typename Word<T>::U pre[4];
+    auto prefetch = [&](const T* buf, int v, typename Word<T>::U* u) {
+        const int sb = sbase[v], m = sm_[v], me = sme[v];
+        const int f = m - 1;
+        const T* rd = buf + sb + me * m;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = k < f ? ld_word(rd + (k < me ? k : k + 1)) : Word<T>::kEmpty;
+    };
+    // all owners' partial sums in owner order: the m - 1 foreign ones
+    // waited for (re-read while empty) and their words emptied
+    auto gather = [&](T* buf, int v, bool prefetched) -> T {
         const int sb = sbase[v], m = sm_[v], me = sme[v];
         const int f = m - 1;
         const T* rd = buf + sb + me * m;
         typename Word<T>::U u[4];
+        if (prefetched) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) u[k] = k < f ? ld_word(rd + (k < me ? k : k + 1)) : Word<T>::kEmpty;
+            for (int k = 0; k < 4; ++k) u[k] = pre[k];
+        } else {
+            prefetch(buf, v, u);
+        }
         T w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) w[k] = k < f ? await_word(rd + (k < me ? k : k + 1), u[k], limit, &ok_lds) : T(0);
@@ -318,12 +336,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         }
         ownp[v] = acc;
         publish(a.bpart, v, acc);
+        if (v == tid && sbase[v] >= 0) prefetch(a.bpart, v, pre);
     }
     __syncthreads();
 
     const int GA = task_lanes(TK, nt);
     // residual sums of all parts for one sweep, as raw words (wave tw, lane l
-    // holds the parts l, l + 64, l + 128, l + 192)
+    // holds the parts l, l + 64, l + 128, l + 192); a sweep's ring entry is
+    // [8][P] doubles, quantity-major, so that a wave's load is contiguous
     unsigned long long pv[4][5];
     auto ring = [&](int64_t sweep) -> double* { return a.rpart + int64_t(sweep & (kRing - 1)) * P * 8; };
     auto issue_ring = [&](int64_t sweep) {
@@ -332,7 +352,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         for (int u = 0; u < 4; ++u) {
             const unsigned p = unsigned(lane) + 64u * u;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) pv[u][q] = p < P ? ld_word(base + p * 8 + q) : 0ull;
+            for (int q = 0; q < 5; ++q) pv[u][q] = p < P ? ld_word(base + q * P + p) : 0ull;
         }
     };
     uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -353,7 +373,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double sq = sqrt(double(a.nloc));
     // termination test of one finished sweep from every part's sums (loads
-    // issued by issue_ring); identical on every workgroup
+    // issued by issue_ring one sweep earlier); identical on every workgroup
     auto decide = [&](int64_t sweep) -> bool {
         if (wv == tw) {
             const double* base = ring(sweep);
@@ -363,7 +383,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                 const unsigned p = unsigned(lane) + 64u * u;
 #pragma unroll
                 for (int q = 0; q < 5; ++q)
-                    if (p < P) acc[q] += await_word(base + p * 8 + q, pv[u][q], limit, &ok_lds);
+                    if (p < P) acc[q] += await_word(base + q * P + p, pv[u][q], limit, &ok_lds);
             }
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
@@ -391,17 +411,19 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     };
 
     bool stopped = false;
+    int cur = 0;  // state buffer of sweep `done` (sweep k lives in buffer k % 3)
     while (done < a.max_iter) {
-        const int cur = int(done & 1), nx = cur ^ 1;
-        T* bcur = a.bpart + int64_t(cur) * ns;
-        T* bnx = a.bpart + int64_t(nx) * ns;
+        const int nx = cur == 2 ? 0 : cur + 1;
+        const int bp = int(done & 1);  // exchange-word parity
+        T* bcur = a.bpart + int64_t(bp) * ns;
+        T* bnx = a.bpart + int64_t(bp ^ 1) * ns;
         T* xg = xl[nx];
         // wave tw's stores (ring words, emptied ring words) complete before
         // it stores again; it waits here, off the critical path
         if (wv == tw && nw > 1) __builtin_amdgcn_s_waitcnt(0);
         // closed_1: clipped average of the copies
         for (int v = tid; tid < g_threads && v < V; v += g_threads) {
-            const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
+            const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v, v == tid);
             T xv = (s - crho[v]) * vcnt[v];
             xv = xv < vlo[v] ? vlo[v] : xv;
             xv = xv > vhi[v] ? vhi[v] : xv;
@@ -418,8 +440,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         for (int r = tid; r < R; r += nt) vb[r] = xg[rlv[r]] + lc[r] * irho;
         __syncthreads();
         stamp(1);
-        // the previous sweep's residual sums of every part, read during this one
-        if (wv == tw && done >= 1) issue_ring(done);
+        // residual sums of every part for sweep done - 1, published a whole
+        // sweep ago, read during this one and tested after it
+        if (wv == tw && done >= 2) issue_ring(done - 1);
         // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
         for (int base = 0; base < TK * GA; base += nt) {
             const int q0 = base + tid;
@@ -501,38 +524,42 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             }
             ownp[v] = acc;
             publish(bnx, v, acc);
+            if (v == tid && sbase[v] >= 0) prefetch(bnx, v, pre);
         }
         if (wv == tw && lane < 5) {
             double acc = 0.0;
             for (int w = 0; w < nw; ++w) acc += red[w * 8 + lane];
-            st_agent(ring(done + 1) + blockIdx.x * 8 + lane, acc);
+            st_agent(ring(done + 1) + lane * P + blockIdx.x, acc);
         }
         stamp(4);
         ++done;
-        // the test of the previous sweep, from sums read during this one
-        if (done >= 2) {
-            const bool stop = decide(done - 1);
+        cur = nx;
+        // the test of sweep done - 2, from sums read during this sweep
+        if (done >= 3) {
+            const bool stop = decide(done - 2);
             if (!ok) break;
             if (stop) {
-                result = done - 1;
+                result = done - 2;
                 stopped = true;
                 break;
             }
-            // every part has read the ring words of sweep done - 3
-            if (wv == tw && lane < 5 && done >= 4) st_empty(ring(done - 3) + blockIdx.x * 8 + lane);
+            // every part has read the ring words of sweep done - 5 (each
+            // part tests sweep j before it publishes sweep j + 3)
+            if (wv == tw && lane < 5 && done >= 6) st_empty(ring(done - 5) + lane * P + blockIdx.x);
         }
         stamp(5);
     }
     if (ok && !stopped) {
-        // the last computed sweep (max_iter reached)
+        // max_iter reached: the sweeps not yet tested, in order
         result = done;
-        if (done > 0) {
-            if (wv == tw) issue_ring(done);
-            decide(done);
+        for (int64_t k = done > 2 ? done - 1 : 1; k <= done; ++k) {
+            if (wv == tw) issue_ring(k);
+            result = k;
+            if (decide(k) || !ok) break;
         }
     }
     // ---- write the state of sweep `result` back (canonical order, FP64)
-    const int fp = int(result & 1);
+    const int fp = int(result % 3);
     for (int r = tid; r < R; r += nt) {
         const int canon = a.row_canon[pi.row_begin + r];
         a.xs[canon] = double(xs[fp][r]);

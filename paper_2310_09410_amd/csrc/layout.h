@@ -14,7 +14,7 @@
 namespace ldopf {
 
 struct LdsLayout {
-    uint32_t W, bbar, xs0, xs1, lam0, lam1, v, t, xloc0, xloc1, ownp, crho, lo, hi, cnt;  // T arrays
+    uint32_t W, bbar, xs[3], lam[3], v, t, xloc[3], ownp, crho, lo, hi, cnt;  // T arrays
     uint32_t slot_lo, slot_hi, slot_own;                                         // int32 per var
     uint32_t row_lvar, row_sub, copy_off, copy_rows, tk_sub, meta;                // index arrays
     uint32_t red;                                                                // double [waves][8]
@@ -35,14 +35,13 @@ LDOPF_HD inline LdsLayout lds_layout(uint32_t w, uint32_t w_words, uint32_t rows
     };
     L.W = take(w * w_words);
     L.bbar = take(w * rows);
-    L.xs0 = take(w * rows);
-    L.xs1 = take(w * rows);
-    L.lam0 = take(w * rows);
-    L.lam1 = take(w * rows);
+    // state of the last three sweeps: the test of sweep k is decided after
+    // sweep k + 2, and a stop returns the state of sweep k
+    for (int b = 0; b < 3; ++b) L.xs[b] = take(w * rows);
+    for (int b = 0; b < 3; ++b) L.lam[b] = take(w * rows);
     L.v = take(w * rows);
     L.t = take(w * tks);
-    L.xloc0 = take(w * vars);
-    L.xloc1 = take(w * vars);
+    for (int b = 0; b < 3; ++b) L.xloc[b] = take(w * vars);
     L.ownp = take(w * vars);
     L.crho = take(w * vars);
     L.lo = take(w * vars);
