@@ -168,6 +168,7 @@ void build_device(ldopf_problem& h) {
     h.x.alloc(lp.n, "x");
     h.bpart.alloc(size_t(2) * std::max(pl.n_slots, 1) * (h.fp32 ? 4 : 8), "boundary slots");
     h.rpart.alloc(size_t(kRing) * pl.n_parts * 8, "residual slots");
+    h.gpart.alloc(size_t(kRing) * 8 * kGroup, "residual group slots");
     h.st.alloc(1, "status");
     h.prof.alloc(8, "phase times");
     init_state(h);
@@ -200,6 +201,7 @@ SweepArgs<T> sweep_args(ldopf_problem& h) {
     a.x = h.x.p;
     a.bpart = reinterpret_cast<T*>(h.bpart.p);
     a.rpart = h.rpart.p;
+    a.gpart = h.gpart.p;
     a.hist = h.hist.p;
     a.hist_cap = h.opts.history ? int64_t(h.hist.count / 4) : 0;
     a.st = h.st.p;

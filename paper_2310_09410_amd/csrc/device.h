@@ -28,12 +28,14 @@ struct PrecomputeArgs {
     double tol_rhs; // ... and then its right-hand side must be below tol_rhs * (1 + max |b_s|)
 };
 
-// Residual sums of every part for the last kRing sweeps: [kRing][8][P]
-// doubles (quantity-major); a part's word is emptied once every part has
-// read it.
+// Residual sums of the last kRing sweeps: every part's ([kRing][8][P]
+// doubles, quantity-major), emptied by its group leader once read, and the
+// sums of each group of kGroup consecutive parts ([kRing][8][kGroup]),
+// emptied by the leader once every part has read them.
 constexpr int kRing = 8;
-// Parts the sweep can run: the reader wave of the test holds four parts per lane.
-constexpr int kMaxParts = 256;
+constexpr int kGroup = 16;
+// Parts the sweep can run: kGroup groups of kGroup parts.
+constexpr int kMaxParts = kGroup * kGroup;
 
 struct SweepStatus {
     int64_t iters;     // sweep whose state is returned
@@ -69,6 +71,7 @@ struct SweepArgs {
     double* x;           // global x out
     T* bpart;            // [2][n_slots] boundary partial sums, one word per (var, writer, reader)
     double* rpart;       // [kRing][8][P] residual partial sums
+    double* gpart;       // [kRing][8][kGroup] residual sums per group of parts
     double* hist;        // [hist_cap][4]
     int64_t hist_cap;
     SweepStatus* st;

@@ -341,19 +341,49 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     __syncthreads();
 
     const int GA = task_lanes(TK, nt);
-    // residual sums of all parts for one sweep, as raw words (wave tw, lane l
-    // holds the parts l, l + 64, l + 128, l + 192); a sweep's ring entry is
-    // [8][P] doubles, quantity-major, so that a wave's load is contiguous
-    unsigned long long pv[4][5];
-    auto ring = [&](int64_t sweep) -> double* { return a.rpart + int64_t(sweep & (kRing - 1)) * P * 8; };
-    auto issue_ring = [&](int64_t sweep) {
-        const double* base = ring(sweep);
+    // Residual sums, reduced in two levels by wave tw. Level 1: every part's
+    // 5 sums of a sweep (ring entry [8][P], quantity-major), read only by its
+    // group leader, the first of each kGroup consecutive parts, which adds
+    // its members' sums (lane l stands for member l) and publishes them
+    // (level 2, ring entry [8][kGroup]); every part then reads the group
+    // sums (lane l stands for group l) and runs the test. Both sums use the
+    // same lane order everywhere, so every part takes the same decision.
+    const bool leader = blockIdx.x % kGroup == 0;
+    const unsigned grp = blockIdx.x / kGroup, ngroups = (P + kGroup - 1) / kGroup;
+    const unsigned member = blockIdx.x + unsigned(lane);
+    const bool mem_in = lane < kGroup && member < P;
+    const bool grp_in = unsigned(lane) < ngroups;
+    unsigned long long w1[5], w2[5];
+    auto ring1 = [&](int64_t sweep) -> double* { return a.rpart + int64_t(sweep & (kRing - 1)) * P * 8; };
+    auto ring2 = [&](int64_t sweep) -> double* { return a.gpart + int64_t(sweep & (kRing - 1)) * 8 * kGroup; };
+    auto issue_members = [&](int64_t sweep) {
+        const double* base = ring1(sweep);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const unsigned p = unsigned(lane) + 64u * u;
+        for (int q = 0; q < 5; ++q) w1[q] = mem_in ? ld_word(base + q * P + member) : 0ull;
+    };
+    auto issue_groups = [&](int64_t sweep) {
+        const double* base = ring2(sweep);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) pv[u][q] = p < P ? ld_word(base + q * P + p) : 0ull;
+        for (int q = 0; q < 5; ++q) w2[q] = grp_in ? ld_word(base + q * kGroup + lane) : 0ull;
+    };
+    // leader: its members' sums of `sweep` added and published; the members'
+    // words emptied (the leader is their only reader)
+    auto group_sums = [&](int64_t sweep) {
+        double* base = ring1(sweep);
+        double v[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            v[q] = mem_in ? await_word(base + q * P + member, w1[q], limit, &ok_lds) : 0.0;
+            v[q] = group_sum(v[q], kGroup);
         }
+        double* g = ring2(sweep);
+        if (lane < 5) {
+            const double t = lane == 0 ? v[0] : (lane == 1 ? v[1] : (lane == 2 ? v[2] : (lane == 3 ? v[3] : v[4])));
+            st_agent(g + lane * kGroup + grp, t);
+        }
+        if (mem_in)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) st_empty(base + q * P + member);
     };
     uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint64_t tlast = 0;
@@ -372,23 +402,16 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     bool ok = true;
     double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double sq = sqrt(double(a.nloc));
-    // termination test of one finished sweep from every part's sums (loads
-    // issued by issue_ring one sweep earlier); identical on every workgroup
+    // termination test of one finished sweep from the group sums (loads
+    // issued by issue_groups during this sweep); identical on every workgroup
     auto decide = [&](int64_t sweep) -> bool {
         if (wv == tw) {
-            const double* base = ring(sweep);
-            double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const unsigned p = unsigned(lane) + 64u * u;
-#pragma unroll
-                for (int q = 0; q < 5; ++q)
-                    if (p < P) acc[q] += await_word(base + q * P + p, pv[u][q], limit, &ok_lds);
-            }
+            const double* base = ring2(sweep);
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                const double t = wave_total(acc[q]);
-                if (lane == 0) tot[q] = t;
+                double v = grp_in ? await_word(base + q * kGroup + lane, w2[q], limit, &ok_lds) : 0.0;
+                v = group_sum(v, kGroup);
+                if (lane == 0) tot[q] = v;
             }
         }
         __syncthreads();
@@ -418,9 +441,6 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         T* bcur = a.bpart + int64_t(bp) * ns;
         T* bnx = a.bpart + int64_t(bp ^ 1) * ns;
         T* xg = xl[nx];
-        // wave tw's stores (ring words, emptied ring words) complete before
-        // it stores again; it waits here, off the critical path
-        if (wv == tw && nw > 1) __builtin_amdgcn_s_waitcnt(0);
         // closed_1: clipped average of the copies
         for (int v = tid; tid < g_threads && v < V; v += g_threads) {
             const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v, v == tid);
@@ -440,9 +460,15 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         for (int r = tid; r < R; r += nt) vb[r] = xg[rlv[r]] + lc[r] * irho;
         __syncthreads();
         stamp(1);
-        // residual sums of every part for sweep done - 1, published a whole
-        // sweep ago, read during this one and tested after it
-        if (wv == tw && done >= 2) issue_ring(done - 1);
+        // wave tw: its earlier stores complete before it stores again (they
+        // were issued a phase or more ago); then the loads of this sweep:
+        // the leader's members' sums of the previous sweep, and the group
+        // sums of sweep done - 1 for the test after this sweep
+        if (wv == tw) {
+            __builtin_amdgcn_s_waitcnt(0);
+            if (leader && done >= 1) issue_members(done);
+            if (done >= 2) issue_groups(done - 1);
+        }
         // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
         for (int base = 0; base < TK * GA; base += nt) {
             const int q0 = base + tid;
@@ -526,10 +552,13 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             publish(bnx, v, acc);
             if (v == tid && sbase[v] >= 0) prefetch(bnx, v, pre);
         }
-        if (wv == tw && lane < 5) {
-            double acc = 0.0;
-            for (int w = 0; w < nw; ++w) acc += red[w * 8 + lane];
-            st_agent(ring(done + 1) + lane * P + blockIdx.x, acc);
+        if (wv == tw) {
+            if (leader && done >= 1) group_sums(done);
+            if (lane < 5) {
+                double acc = 0.0;
+                for (int w = 0; w < nw; ++w) acc += red[w * 8 + lane];
+                st_agent(ring1(done + 1) + lane * P + blockIdx.x, acc);
+            }
         }
         stamp(4);
         ++done;
@@ -543,17 +572,23 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                 stopped = true;
                 break;
             }
-            // every part has read the ring words of sweep done - 5 (each
-            // part tests sweep j before it publishes sweep j + 3)
-            if (wv == tw && lane < 5 && done >= 6) st_empty(ring(done - 5) + lane * P + blockIdx.x);
+            // every part has read the group sums of sweep done - 5 (each part
+            // tests sweep j before it publishes sweep j + 3)
+            if (wv == tw && leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
         }
         stamp(5);
     }
     if (ok && !stopped) {
-        // max_iter reached: the sweeps not yet tested, in order
+        // max_iter reached: the group sums of the last sweep, then the
+        // sweeps not yet tested, in order
         result = done;
+        if (wv == tw && leader && done >= 1) {
+            __builtin_amdgcn_s_waitcnt(0);
+            issue_members(done);
+            group_sums(done);
+        }
         for (int64_t k = done > 2 ? done - 1 : 1; k <= done; ++k) {
-            if (wv == tw) issue_ring(k);
+            if (wv == tw) issue_groups(k);
             result = k;
             if (decide(k) || !ok) break;
         }
@@ -585,12 +620,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
 // Before every sweep launch, on the same stream: every exchange word empty,
 // the status cleared (plain stores).
 template <typename T>
-__global__ void reset_sync_kernel(T* bpart, int64_t n_bwords, double* rpart, int64_t n_rwords, SweepStatus* st) {
+__global__ void reset_sync_kernel(T* bpart, int64_t n_bwords, double* rpart, int64_t n_rwords, double* gpart,
+                                  int64_t n_gwords, SweepStatus* st) {
     const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x, stride = int64_t(gridDim.x) * blockDim.x;
     using UB = typename Word<T>::U;
     using UR = typename Word<double>::U;
     for (int64_t i = i0; i < n_bwords; i += stride) reinterpret_cast<UB*>(bpart)[i] = Word<T>::kEmpty;
     for (int64_t i = i0; i < n_rwords; i += stride) reinterpret_cast<UR*>(rpart)[i] = Word<double>::kEmpty;
+    for (int64_t i = i0; i < n_gwords; i += stride) reinterpret_cast<UR*>(gpart)[i] = Word<double>::kEmpty;
     if (i0 == 0) {
         st->iters = 0;
         st->computed = 0;
@@ -631,8 +668,10 @@ hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_p
 template <typename T>
 static hipError_t launch_sweep_t(const SweepArgs<T>& a, int grid, int block, size_t lds, hipStream_t stream) {
     const int64_t nb = 2 * std::max<int64_t>(a.n_slots, 1), nr = int64_t(kRing) * a.P * 8;
+    const int64_t ng = int64_t(kRing) * 8 * kGroup;
     const unsigned rgrid = unsigned(std::min<int64_t>(256, (std::max(nb, nr) + 255) / 256));
-    hipLaunchKernelGGL(reset_sync_kernel<T>, dim3(rgrid), dim3(256), 0, stream, a.bpart, nb, a.rpart, nr, a.st);
+    hipLaunchKernelGGL(reset_sync_kernel<T>, dim3(rgrid), dim3(256), 0, stream, a.bpart, nb, a.rpart, nr, a.gpart, ng,
+                       a.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     SweepArgs<T> copy = a;

@@ -36,7 +36,7 @@ struct ldopf_problem {
     bool have_x = false;
     uint64_t spin_limit = 0;
 
-    DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart, prof;
+    DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart, gpart, prof;
     double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double tick_ms = 1e-5;  // wall-clock tick in ms
     DevBuf<int32_t> ns, ms, rank_d, flags;
