@@ -34,6 +34,11 @@ WORKLOAD = ("8500-bus synthetic radial 3-phase feeder (seed 8500; 20/10/70% thre
             "plain FP64 ADMM to eps_rel = 1e-4, rho = 100")
 
 
+def progress(msg: str) -> None:
+    """One line on stderr per finished part of the run (stdout carries only the result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes_per_sweep(sizes, w: int) -> float:
     """Compulsory bytes of one sweep: the rank-form operators and bbar, the
     local copies' x_s and lambda read and written plus their int32 global
@@ -112,7 +117,7 @@ def run_serving(P, make_feeder, n_req: int, seed: int = 7):
     import numpy as np
     rng = np.random.default_rng(seed)
     sizes = ["13", "123", "2500", "8500"]
-    est_s = {"13": 0.008, "123": 0.09, "2500": 1.8, "8500": 3.4}  # serial solve times, measured before
+    est_s = {"13": 0.005, "123": 0.05, "2500": 1.1, "8500": 2.0}  # serial solve times, measured before
     rate = 0.9 / (sum(est_s.values()) / 4)
     plan = []
     t = 0.0
@@ -227,6 +232,7 @@ def main():
         return prob, st, iters, computed, kms, dt
 
     prob, st, iters, computed, kms, dt = run(L.LDOPF_FP64)
+    progress(f"fp64: {args.steps} solves in {dt:.2f} s")
     sizes = prob.sizes()
     obj = prob.objective()
     b_sweep = algorithmic_bytes_per_sweep(sizes, 8)
@@ -263,6 +269,7 @@ def main():
     prob.close()
     if not args.no_fp32:
         p32, st32, it32, c32, k32, dt32 = run(L.LDOPF_FP32_MIXED)
+        progress(f"fp32-mixed: {args.steps} solves in {dt32:.2f} s")
         s32 = p32.sizes()
         rec["fp32_mixed"] = {"iter_per_s": it32 / dt32, "iterations_to_tol": st32.iterations,
                              "time_to_tol_s": 1e-3 * sum(k32) / len(k32),
@@ -273,10 +280,13 @@ def main():
         p32.close()
     if not args.no_batched:
         rec["batched"] = run_batched(P, L, make_feeder, scenario_factors, stream)
+        progress(f"batched: {rec['batched']['solves_per_s']:.2f} solves/s")
     if not args.no_serving:
         rec["serving"] = run_serving(P, make_feeder, args.serving_requests)
+        progress("serving done")
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args.cpu_sweeps)
+        progress("cpu baseline done")
     print(json.dumps(rec))
 
 

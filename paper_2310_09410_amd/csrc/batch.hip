@@ -278,6 +278,9 @@ __global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
     const int Bp = a.Bp;
     const int sc = blockIdx.y * kTile + lane;
     const bool on = a.active[sc] != 0;
+    // a tile whose scenarios have all stopped is skipped (its partial rows
+    // are not read: the test runs only for active scenarios)
+    if (__syncthreads_or(on) == 0) return;
     const float rho = float(a.rho), irho = float(1.0 / a.rho);
     double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
     // read-only tables through the constant address space (scalar loads)
@@ -469,8 +472,11 @@ __global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int sc = blockIdx.x * kTile + lane;
     double acc[5] = {0, 0, 0, 0, 0};
+    // a tile whose scenarios have all stopped reads nothing, but still
+    // arrives at the block count below
+    const int rows = __syncthreads_or(a.active[sc] != 0) ? a.part_rows : 0;
     int r = wv;
-    for (; r + 16 < a.part_rows; r += 32) {
+    for (; r + 16 < rows; r += 32) {
         double u[5], w[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
@@ -480,7 +486,7 @@ __global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[q] += u[q] + w[q];
     }
-    if (r < a.part_rows)
+    if (r < rows)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[q] += a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
 #pragma unroll
