@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--profile-pass", action="store_true",
                     help="one copy of known size and one solve, for rocprofv3 counter runs")
+    ap.add_argument("--profile-batched", type=int, default=0, metavar="SWEEPS",
+                    help="only the batched workload: tune, then SWEEPS fixed sweeps, for rocprofv3 runs")
     ap.add_argument("--cpu-baseline-only", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_baseline_only:
@@ -198,6 +200,22 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     net = make_feeder("8500", 8500)
+
+    if args.profile_batched:
+        bnet = make_feeder("2500", 2500)
+        b = P.ldopf_batch_create(bnet, scenario_factors(bnet, 256), stream=stream)
+        r, w = b.tune(None)
+        b.set_options(P.ldopf_default_options(precision=L.LDOPF_FP32_MIXED, max_iter=args.profile_batched,
+                                              check_termination=0))
+        b.reset()
+        st = b.solve()
+        bs = b.sizes()
+        us = 1e3 * st.solve_ms / max(1, st.sweeps)
+        print(json.dumps({"sweeps": st.sweeps, "us_per_batched_sweep": us, "rows_per_chunk": r, "blocks_per_tile": w,
+                          "bytes_per_batched_sweep": batched_bytes_per_sweep(bs),
+                          "achieved_GBs": batched_bytes_per_sweep(bs) / (us * 1e-6) / 1e9}))
+        b.close()
+        return
 
     if args.profile_pass:
         n = 256 << 20  # 1 GiB of float32 read and 1 GiB written: past the 256 MB cache

@@ -50,6 +50,7 @@ namespace {
 constexpr int kTile = 64;  // scenarios per wave
 constexpr int kZS = 80;    // LDS row stride (floats) of the local update
 constexpr int kVPW = 4;    // variables per wave in the global update
+constexpr int kRedBlocks = 8;  // reduction blocks per scenario tile
 
 struct PrecomputeBatchArgs {
     int64_t S, nloc, words;
@@ -150,6 +151,8 @@ struct BatchArgs {
     // residuals and control
     double* part;      // [part_rows][5][Bp]
     int32_t part_rows;
+    double* part2;     // [tiles][kRedBlocks][5][64] slice sums of the reduction
+    int32_t* tick;     // [tiles] reduction blocks finished, per tile
     int32_t* active;   // [Bp]
     int32_t* conv;     // [Bp]
     int64_t* iters;    // [Bp]
@@ -461,22 +464,28 @@ __global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
     }
 }
 
-// Residual sums per scenario over the local blocks' partial rows (16 waves,
-// wave w adds rows w, w + 16, ...; then the waves in order), the termination
-// test, the masks; the last block to finish advances the sweep counter and
-// decides whether the batch is done.
+// Residual sums per scenario over the local blocks' partial rows, in two
+// levels: kRedBlocks blocks per scenario tile each add a contiguous slice of
+// the rows (16 waves, wave w adds rows w, w + 16, ...; then the waves in
+// order) and store the slice sums; the last block of the tile to finish (a
+// ticket per tile) adds the slices in order and runs the termination test,
+// the masks; the last tile to finish advances the sweep counter and decides
+// whether the batch is done. The order of every sum is fixed.
 __global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
     if (a.ctrl[1]) return;
     __shared__ double red[16][5][64];
     __shared__ int last;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int sc = blockIdx.x * kTile + lane;
-    double acc[5] = {0, 0, 0, 0, 0};
+    const int tile = blockIdx.x / kRedBlocks, rb = blockIdx.x % kRedBlocks;
+    const int sc = tile * kTile + lane;
     // a tile whose scenarios have all stopped reads nothing, but still
-    // arrives at the block count below
-    const int rows = __syncthreads_or(a.active[sc] != 0) ? a.part_rows : 0;
-    int r = wv;
-    for (; r + 16 < rows; r += 32) {
+    // arrives at the counts below
+    const bool any = __syncthreads_or(a.active[sc] != 0);
+    const int per = (a.part_rows + kRedBlocks - 1) / kRedBlocks;
+    const int r0 = min(a.part_rows, rb * per), r1 = any ? min(a.part_rows, r0 + per) : r0;
+    double acc[5] = {0, 0, 0, 0, 0};
+    int r = r0 + wv;
+    for (; r + 16 < r1; r += 32) {
         double u[5], w[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
@@ -486,19 +495,35 @@ __global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[q] += u[q] + w[q];
     }
-    if (r < rows)
+    if (r < r1)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[q] += a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
 #pragma unroll
     for (int q = 0; q < 5; ++q) red[wv][q][lane] = acc[q];
-    const int64_t t_now = a.ctrl[0] + 1;
     __syncthreads();
+    double* slice = a.part2 + int64_t(tile) * kRedBlocks * 5 * kTile;
+    if (wv == 0)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            double t = 0.0;
+            for (int w = 0; w < 16; ++w) t += red[w][q][lane];
+            slice[(rb * 5 + q) * kTile + lane] = t;
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&a.tick[tile], 1) == kRedBlocks - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int64_t t_now = a.ctrl[0] + 1;
     if (wv == 0) {
         double d[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             double t = 0.0;
-            for (int w = 0; w < 16; ++w) t += red[w][q][lane];
+            for (int b2 = 0; b2 < kRedBlocks; ++b2) t += slice[(b2 * 5 + q) * kTile + lane];
             d[q] = t;
         }
         int still = 0;
@@ -520,22 +545,23 @@ __global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
             if (!still) a.active[sc] = 0;
         }
         const unsigned long long ball = __ballot(still);
-        if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), (unsigned long long)__popcll(ball));
+        if (lane == 0) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), (unsigned long long)__popcll(ball));
+            a.tick[tile] = 0;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         const unsigned long long prev = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[3]), 1ull);
-        last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        const long long left = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), 0ull);
-        a.ctrl[0] = t_now;
-        a.ctrl[2] = 0;
-        a.ctrl[3] = 0;
-        a.ctrl[1] = (left == 0 || t_now >= a.max_iter) ? 1 : 0;
+        if (prev == unsigned(a.Bp / kTile) - 1) {
+            __threadfence();
+            const long long left = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), 0ull);
+            a.ctrl[0] = t_now;
+            a.ctrl[2] = 0;
+            a.ctrl[3] = 0;
+            a.ctrl[1] = (left == 0 || t_now >= a.max_iter) ? 1 : 0;
+        }
     }
 }
 
@@ -558,6 +584,7 @@ __global__ void batch_init_kernel(BatchArgs a, const double* x_init) {
         for (int q = 0; q < 4; ++q) a.res[sc * 4 + q] = 0.0;
     }
     if (i < 4) a.ctrl[i] = 0;
+    if (i < a.Bp / kTile) a.tick[i] = 0;
 }
 
 }  // namespace
@@ -587,8 +614,8 @@ struct ldopf_batch {
     DevBuf<int4> ell;
     DevBuf<int64_t> loc_off, wofs, iters, ctrl;
     DevBuf<float> crho, lo, hi, invN, X, XS, LAM, BB, ash, W;
-    DevBuf<double> x_init, part, res;
-    DevBuf<int32_t> active, conv, sflags;
+    DevBuf<double> x_init, part, part2, res;
+    DevBuf<int32_t> active, conv, sflags, tick;
 
     ~ldopf_batch() {
         if (stream) (void)hipStreamSynchronize(stream);
@@ -631,6 +658,8 @@ BatchArgs batch_args(ldopf_batch& h) {
     a.W = h.W.p;
     a.part = h.part.p;
     a.part_rows = h.grid;
+    a.part2 = h.part2.p;
+    a.tick = h.tick.p;
     a.active = h.active.p;
     a.conv = h.conv.p;
     a.iters = h.iters.p;
@@ -665,7 +694,7 @@ void enqueue_sweep(ldopf_batch& h, const BatchArgs& a) {
     BatchArgs copy = a;
     void* args[] = {&copy};
     (void)hipLaunchKernel(local_kernel(h.rpw), dim3(h.grid, tiles), dim3(256), args, local_lds(h), h.stream);
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(tiles), dim3(1024), 0, h.stream, a);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(tiles * kRedBlocks), dim3(1024), 0, h.stream, a);
 }
 
 // Chunks of the subsystem order: consecutive subsystems up to rows_per_chunk copies.
@@ -1067,6 +1096,8 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             h->iters.alloc(Bp, "iterations");
             h->res.alloc(size_t(Bp) * 4, "residuals");
             h->ctrl.alloc(4, "control");
+            h->part2.alloc(size_t(Bp / kTile) * kRedBlocks * 5 * kTile, "residual slices");
+            h->tick.alloc(size_t(Bp / kTile), "reduction tickets");
             const int32_t rows = o.rows_per_part > 0 ? o.rows_per_part : 64;
             set_chunks(*h, rows, 256);
             batch_reset(*h);
