@@ -197,12 +197,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                                    uint32_t(pi.n_var), uint32_t(pi.n_sub), uint32_t(nw));
     T* W = reinterpret_cast<T*>(smem + L.W);
     T* bbar = reinterpret_cast<T*>(smem + L.bbar);
-    T* xs[3] = {reinterpret_cast<T*>(smem + L.xs[0]), reinterpret_cast<T*>(smem + L.xs[1]),
-                reinterpret_cast<T*>(smem + L.xs[2])};
-    T* lam[3] = {reinterpret_cast<T*>(smem + L.lam[0]), reinterpret_cast<T*>(smem + L.lam[1]),
-                 reinterpret_cast<T*>(smem + L.lam[2])};
-    T* xl[3] = {reinterpret_cast<T*>(smem + L.xloc[0]), reinterpret_cast<T*>(smem + L.xloc[1]),
-                reinterpret_cast<T*>(smem + L.xloc[2])};
+    // state buffers, selected by offset from the shared base so that every
+    // access stays an LDS access (a table of pointers would not)
+    const uint32_t s_xs = L.xs[1] - L.xs[0], s_lam = L.lam[1] - L.lam[0], s_xl = L.xloc[1] - L.xloc[0];
+    auto XS = [&](int b) { return reinterpret_cast<T*>(smem + L.xs[0] + uint32_t(b) * s_xs); };
+    auto LAM = [&](int b) { return reinterpret_cast<T*>(smem + L.lam[0] + uint32_t(b) * s_lam); };
+    auto XL = [&](int b) { return reinterpret_cast<T*>(smem + L.xloc[0] + uint32_t(b) * s_xl); };
     T* vb = reinterpret_cast<T*>(smem + L.v);
     T* tb = reinterpret_cast<T*>(smem + L.t);
     T* ownp = reinterpret_cast<T*>(smem + L.ownp);
@@ -238,8 +238,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     for (int r = tid; r < R; r += nt) {
         const int canon = a.row_canon[pi.row_begin + r];
         bbar[r] = T(a.bbar[canon]);
-        xs[0][r] = T(a.xs[canon]);
-        lam[0][r] = T(a.lam[canon]);
+        XS(0)[r] = T(a.xs[canon]);
+        LAM(0)[r] = T(a.lam[canon]);
         rlv[r] = a.row_lvar[pi.row_begin + r];
         rsub[r] = a.row_sub[pi.row_begin + r];
         crow[r] = a.var_copy_rows[pi.copy_begin + r];
@@ -282,9 +282,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             if (j != me) st_agent(buf + sb + j * m + me, acc);
     };
     // the words addressed to this part for a boundary variable (up to four
-    // loads in flight); a thread loads those of its first variable right
-    // after publishing, so that they travel while the test runs
-    typename Word<T>::U pre[4];
+    // loads in flight)
     auto prefetch = [&](const T* buf, int v, typename Word<T>::U* u) {
         const int sb = sbase[v], m = sm_[v], me = sme[v];
         const int f = m - 1;
@@ -294,17 +292,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     };
     // all owners' partial sums in owner order: the m - 1 foreign ones
     // waited for (re-read while empty) and their words emptied
-    auto gather = [&](T* buf, int v, bool prefetched) -> T {
+    auto gather = [&](T* buf, int v) -> T {
         const int sb = sbase[v], m = sm_[v], me = sme[v];
         const int f = m - 1;
         const T* rd = buf + sb + me * m;
         typename Word<T>::U u[4];
-        if (prefetched) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) u[k] = pre[k];
-        } else {
-            prefetch(buf, v, u);
-        }
+        prefetch(buf, v, u);
         T w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) w[k] = k < f ? await_word(rd + (k < me ? k : k + 1), u[k], limit, &ok_lds) : T(0);
@@ -332,11 +325,10 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         T acc = T(0);
         for (int q = coff[v]; q < coff[v + 1]; ++q) {
             const int r = crow[q];
-            acc += xs[0][r] - lam[0][r] * irho;
+            acc += XS(0)[r] - LAM(0)[r] * irho;
         }
         ownp[v] = acc;
         publish(a.bpart, v, acc);
-        if (v == tid && sbase[v] >= 0) prefetch(a.bpart, v, pre);
     }
     __syncthreads();
 
@@ -402,19 +394,22 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     bool ok = true;
     double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const double sq = sqrt(double(a.nloc));
-    // termination test of one finished sweep from the group sums (loads
-    // issued by issue_groups during this sweep); identical on every workgroup
-    auto decide = [&](int64_t sweep) -> bool {
-        if (wv == tw) {
-            const double* base = ring2(sweep);
+    // termination test of one finished sweep; identical on every workgroup
+    // wave tw: the grid-wide sums of one sweep from the group sums (loads
+    // issued by issue_groups), into LDS for every thread
+    auto totals = [&](int64_t sweep) {
+        const double* base = ring2(sweep);
+        double v[5];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                double v = grp_in ? await_word(base + q * kGroup + lane, w2[q], limit, &ok_lds) : 0.0;
-                v = group_sum(v, kGroup);
-                if (lane == 0) tot[q] = v;
-            }
-        }
-        __syncthreads();
+        for (int q = 0; q < 5; ++q) v[q] = grp_in ? await_word(base + q * kGroup + lane, w2[q], limit, &ok_lds) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[q] = group_sum(v[q], kGroup);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) tot[q] = v[q];
+    };
+    // the test of one sweep from the totals in LDS (after a block barrier)
+    auto decide = [&](int64_t sweep) -> bool {
         ok = ok_lds != 0;
 #pragma unroll
         for (int q = 0; q < 5; ++q) d[q] = tot[q];
@@ -434,16 +429,19 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     };
 
     bool stopped = false;
-    int cur = 0;  // state buffer of sweep `done` (sweep k lives in buffer k % 3)
+    int cur = 0;  // x_s, lambda buffer of sweep `done` (sweep k lives in buffer k % 3, its x in k % 4)
     while (done < a.max_iter) {
         const int nx = cur == 2 ? 0 : cur + 1;
         const int bp = int(done & 1);  // exchange-word parity
         T* bcur = a.bpart + int64_t(bp) * ns;
         T* bnx = a.bpart + int64_t(bp ^ 1) * ns;
-        T* xg = xl[nx];
+        T* xg = XL(int((done + 1) & 3));
+        // the test of sweep done - 2 overlaps this global update: wave tw
+        // forms the totals now, every thread reads them after the barrier
+        if (wv == tw && done >= 3) totals(done - 2);
         // closed_1: clipped average of the copies
         for (int v = tid; tid < g_threads && v < V; v += g_threads) {
-            const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v, v == tid);
+            const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
             T xv = (s - crho[v]) * vcnt[v];
             xv = xv < vlo[v] ? vlo[v] : xv;
             xv = xv > vhi[v] ? vhi[v] : xv;
@@ -454,9 +452,21 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             ok = false;
             break;
         }
+        if (done >= 3) {
+            if (decide(done - 2)) {
+                // x_s, lambda of sweep done - 2 are intact (this sweep's
+                // local update has not run), and so is its x (buffer % 4)
+                result = done - 2;
+                stopped = true;
+                break;
+            }
+            // every part has read the group sums of sweep done - 5 (each part
+            // tests sweep j before it publishes sweep j + 3)
+            if (wv == tw && leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
+        }
         stamp(0);
         // v = B_s x + lambda_s / rho
-        const T* lc = lam[cur];
+        const T* lc = LAM(cur);
         for (int r = tid; r < R; r += nt) vb[r] = xg[rlv[r]] + lc[r] * irho;
         __syncthreads();
         stamp(1);
@@ -494,9 +504,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         stamp(2);
         // closed_2 in rank form, then ADMM-3; residual sums in FP64
         double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
-        const T* xc = xs[cur];
-        T* xn = xs[nx];
-        T* ln = lam[nx];
+        const T* xc = XS(cur);
+        T* xn = XS(nx);
+        T* ln = LAM(nx);
         for (int r = tid; r < R; r += nt) {
             const SubLds m = meta[rsub[r]];
             const int j = r - m.row0;
@@ -550,7 +560,6 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             }
             ownp[v] = acc;
             publish(bnx, v, acc);
-            if (v == tid && sbase[v] >= 0) prefetch(bnx, v, pre);
         }
         if (wv == tw) {
             if (leader && done >= 1) group_sums(done);
@@ -563,19 +572,6 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         stamp(4);
         ++done;
         cur = nx;
-        // the test of sweep done - 2, from sums read during this sweep
-        if (done >= 3) {
-            const bool stop = decide(done - 2);
-            if (!ok) break;
-            if (stop) {
-                result = done - 2;
-                stopped = true;
-                break;
-            }
-            // every part has read the group sums of sweep done - 5 (each part
-            // tests sweep j before it publishes sweep j + 3)
-            if (wv == tw && leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
-        }
         stamp(5);
     }
     if (ok && !stopped) {
@@ -587,22 +583,27 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             issue_members(done);
             group_sums(done);
         }
-        for (int64_t k = done > 2 ? done - 1 : 1; k <= done; ++k) {
-            if (wv == tw) issue_groups(k);
+        for (int64_t k = done > 3 ? done - 2 : 1; k <= done; ++k) {
+            if (wv == tw) {
+                issue_groups(k);
+                totals(k);
+            }
+            __syncthreads();
             result = k;
             if (decide(k) || !ok) break;
+            __syncthreads();  // tot is rewritten for the next sweep
         }
     }
     // ---- write the state of sweep `result` back (canonical order, FP64)
-    const int fp = int(result % 3);
+    const int fp = int(result % 3), fx = int(result & 3);
     for (int r = tid; r < R; r += nt) {
         const int canon = a.row_canon[pi.row_begin + r];
-        a.xs[canon] = double(xs[fp][r]);
-        a.lam[canon] = double(lam[fp][r]);
+        a.xs[canon] = double(XS(fp)[r]);
+        a.lam[canon] = double(LAM(fp)[r]);
     }
     if (result > 0)
         for (int v = tid; v < V; v += nt)
-            if (a.var_writer[pi.var_begin + v]) a.x[a.var_gid[pi.var_begin + v]] = double(xl[fp][v]);
+            if (a.var_writer[pi.var_begin + v]) a.x[a.var_gid[pi.var_begin + v]] = double(XL(fx)[v]);
     if (tid == 0 && (!ok || nonfinite)) atomicOr(&a.st->flags, (ok ? 0 : 1) | (nonfinite ? 2 : 0));
     if (blockIdx.x == 0 && tid == 0) {
         a.st->iters = result;

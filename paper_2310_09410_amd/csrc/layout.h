@@ -14,7 +14,7 @@
 namespace ldopf {
 
 struct LdsLayout {
-    uint32_t W, bbar, xs[3], lam[3], v, t, xloc[3], ownp, crho, lo, hi, cnt;  // T arrays
+    uint32_t W, bbar, xs[3], lam[3], v, t, xloc[4], ownp, crho, lo, hi, cnt;  // T arrays
     uint32_t slot_lo, slot_hi, slot_own;                                         // int32 per var
     uint32_t row_lvar, row_sub, copy_off, copy_rows, tk_sub, meta;                // index arrays
     uint32_t red;                                                                // double [waves][8]
@@ -35,13 +35,14 @@ LDOPF_HD inline LdsLayout lds_layout(uint32_t w, uint32_t w_words, uint32_t rows
     };
     L.W = take(w * w_words);
     L.bbar = take(w * rows);
-    // state of the last three sweeps: the test of sweep k is decided after
-    // sweep k + 2, and a stop returns the state of sweep k
+    // state of the last sweeps: the test of sweep k is decided during the
+    // global update of sweep k + 3, and a stop returns the state of sweep k
+    // (x_s, lambda of sweeps k .. k + 2; x of sweeps k .. k + 3)
     for (int b = 0; b < 3; ++b) L.xs[b] = take(w * rows);
     for (int b = 0; b < 3; ++b) L.lam[b] = take(w * rows);
     L.v = take(w * rows);
     L.t = take(w * tks);
-    for (int b = 0; b < 3; ++b) L.xloc[b] = take(w * vars);
+    for (int b = 0; b < 4; ++b) L.xloc[b] = take(w * vars);
     L.ownp = take(w * vars);
     L.crho = take(w * vars);
     L.lo = take(w * vars);
