@@ -260,11 +260,14 @@ LDOPF_API int ldopf_get_history(const ldopf_problem* h, double* hist, int64_t ca
 LDOPF_API int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t cap_abar,
                                   double* bbar, int64_t cap_bbar, int32_t* rank, int64_t cap_rank);
 /* Per-phase device time of the last solve with options.profile = 1, in ms,
- * measured by workgroup 0 with the wall clock: [0] global update, [1]
- * gather of B_s x + lambda/rho, [2] t = W v, [3] local and dual update with
- * residual sums, [4] partial sums and publication, [5] grid barrier,
- * [6] termination test, [7] unused. Zeros when profiling was off. */
+ * measured by workgroup 0 with the wall clock: [0] global update, with the
+ * wait for the neighbours' partial sums and the termination test of an
+ * earlier sweep, [1] gather of B_s x + lambda/rho, [2] t = W v, [3] local
+ * and dual update with residual sums, [4] partial sums and publication,
+ * [5] end of the sweep, [6], [7] unused. Zeros when profiling was off. */
 LDOPF_API int ldopf_get_phase_times(const ldopf_problem* h, double ms[8]);
+/* The same for workgroup `part` (0 <= part < ldopf_sizes.n_parts). */
+LDOPF_API int ldopf_get_phase_times_part(const ldopf_problem* h, int32_t part, double ms[8]);
 
 /* c'x at the last sweep's global x. */
 LDOPF_API int ldopf_objective(const ldopf_problem* h, double* f);

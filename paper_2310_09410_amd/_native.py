@@ -125,6 +125,7 @@ SIGNATURES = {
     "ldopf_get_history": (C.c_int, [C.c_void_p, _d, C.c_int64, _i64]),
     "ldopf_get_operators": (C.c_int, [C.c_void_p, _d, C.c_int64, _d, C.c_int64, _i32, C.c_int64]),
     "ldopf_get_phase_times": (C.c_int, [C.c_void_p, _d]),
+    "ldopf_get_phase_times_part": (C.c_int, [C.c_void_p, C.c_int32, _d]),
     "ldopf_objective": (C.c_int, [C.c_void_p, _d]),
     "ldopf_get_global_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "ldopf_get_local_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),

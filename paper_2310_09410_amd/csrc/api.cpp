@@ -170,7 +170,7 @@ void build_device(ldopf_problem& h) {
     h.rpart.alloc(size_t(kRing) * pl.n_parts * 8, "residual slots");
     h.gpart.alloc(size_t(kRing) * 8 * kGroup, "residual group slots");
     h.st.alloc(1, "status");
-    h.prof.alloc(8, "phase times");
+    h.prof.alloc(size_t(8) * std::max(pl.n_parts, 1), "phase times");
     init_state(h);
 }
 
@@ -290,11 +290,11 @@ int problem_finish(ldopf_problem& h, ldopf_status* status) {
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, h.ev0, h.ev1), "event time");
     h.last_sweep_ms = ms;
-    std::fill(h.phase_ms, h.phase_ms + 8, 0.0);
+    h.phase_ms.assign(size_t(8) * std::max(h.plan.n_parts, 1), 0.0);
     if (h.opts.profile) {
-        double ticks[8];
-        hip_check(hipMemcpy(ticks, h.prof.p, sizeof(ticks), hipMemcpyDeviceToHost), "download phase times");
-        for (int i = 0; i < 8; ++i) h.phase_ms[i] = ticks[i] * h.tick_ms;
+        hip_check(hipMemcpy(h.phase_ms.data(), h.prof.p, h.phase_ms.size() * 8, hipMemcpyDeviceToHost),
+                  "download phase times");
+        for (double& t : h.phase_ms) t *= h.tick_ms;
     }
     h.hist_len = h.opts.history ? std::min<int64_t>(st.iters, int64_t(h.hist.count / 4)) : 0;
     if (st.iters > 0) h.have_x = true;
@@ -618,10 +618,16 @@ int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t cap_abar, 
 }
 
 int ldopf_get_phase_times(const ldopf_problem* h, double* ms) {
+    return ldopf_get_phase_times_part(h, 0, ms);
+}
+
+int ldopf_get_phase_times_part(const ldopf_problem* h, int32_t part, double* ms) {
     return guard([&] {
         need(h, "handle");
         need(ms, "ms");
-        std::memcpy(ms, h->phase_ms, sizeof(h->phase_ms));
+        if (part < 0 || part >= std::max(h->plan.n_parts, 1)) fail(LDOPF_INVALID_ARGUMENT, "part out of range");
+        for (int i = 0; i < 8; ++i)
+            ms[i] = size_t(part) * 8 + i < h->phase_ms.size() ? h->phase_ms[size_t(part) * 8 + i] : 0.0;
     });
 }
 

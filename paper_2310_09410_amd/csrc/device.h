@@ -82,7 +82,7 @@ struct SweepArgs {
     int32_t check;
     int32_t P;
     uint64_t spin_limit; // wall-clock ticks an exchange wait may take
-    double* prof;        // nullable: per-phase wall-clock ticks of workgroup 0 (8 entries)
+    double* prof;        // nullable: per-phase wall-clock ticks of every workgroup ([P][8])
 };
 
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream);

@@ -78,12 +78,22 @@ __device__ inline double read_lane(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// Sum over the 64 lanes of a wave without LDS traffic: row sums by DPP, then
-// the four row sums in a fixed order. The result is wave-uniform and the same
-// on every wave given the same inputs. Needs every lane of the wave active.
-__device__ inline double wave_total(double v) {
-    v = group_sum(v, 16);
-    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+// Sums over the 64 lanes of a wave of five values, without LDS traffic: row
+// sums by DPP, then the four row sums in a fixed order. Results are
+// wave-uniform and the same on every wave given the same inputs. The steps
+// run across the five values so that their DPP chains overlap. Needs every
+// lane of the wave active.
+__device__ inline void wave_total5(double* v) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[q] += dpp_move<kDppXor1>(v[q]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[q] += dpp_move<kDppXor2>(v[q]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[q] += dpp_move<kDppHalfMirror>(v[q]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[q] += dpp_move<kDppMirror>(v[q]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[q] = (read_lane(v[q], 0) + read_lane(v[q], 16)) + (read_lane(v[q], 32) + read_lane(v[q], 48));
 }
 
 __device__ inline void st_agent(double* p, double v) {
@@ -380,13 +390,13 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint64_t tlast = 0;
     auto stamp = [&](int ph) {
-        if (PROF && blockIdx.x == 0 && tid == 0) {
+        if (PROF && tid == 0) {
             const uint64_t now = wall_clock64();
             tprof[ph] += now - tlast;
             tlast = now;
         }
     };
-    if (PROF && blockIdx.x == 0 && tid == 0) tlast = wall_clock64();
+    if (PROF && tid == 0) tlast = wall_clock64();
 
     int64_t done = 0;     // sweeps computed
     int64_t result = 0;   // sweep whose state is returned
@@ -488,14 +498,19 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                 const SubLds m = meta[tks[task]];
                 const T* wr = W + m.w0 + (task - m.t0) * m.n;
                 const T* vv = vb + m.row0;
-                T acc1 = T(0);
+                // four products per step, their eight loads issued together
+                T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
                 int j = sub;
-                for (; j + GA < m.n; j += 2 * GA) {
-                    acc += wr[j] * vv[j];
-                    acc1 += wr[j + GA] * vv[j + GA];
+                for (; j + 3 * GA < m.n; j += 4 * GA) {
+                    const T w0 = wr[j], w1 = wr[j + GA], w2 = wr[j + 2 * GA], w3 = wr[j + 3 * GA];
+                    const T v0 = vv[j], v1 = vv[j + GA], v2 = vv[j + 2 * GA], v3 = vv[j + 3 * GA];
+                    a0 += w0 * v0;
+                    a1 += w1 * v1;
+                    a2 += w2 * v2;
+                    a3 += w3 * v3;
                 }
-                if (j < m.n) acc += wr[j] * vv[j];
-                acc += acc1;
+                for (; j < m.n; j += GA) a0 += wr[j] * vv[j];
+                acc = (a0 + a1) + (a2 + a3);
             }
             acc = group_sum(acc, GA);
             if (task < TK && sub == 0) tb[task] = acc;
@@ -512,14 +527,20 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             const int j = r - m.row0;
             const T* wc = W + m.w0 + j;
             const T* tt = tb + m.t0;
-            T acc = T(0), acc1 = T(0);
+            // four products per step, their eight loads issued together
+            const int n_ = m.n, K_ = m.k;
+            T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
             int k = 0;
-            for (; k + 1 < m.k; k += 2) {
-                acc += wc[k * m.n] * tt[k];
-                acc1 += wc[(k + 1) * m.n] * tt[k + 1];
+            for (; k + 4 <= K_; k += 4) {
+                const T w0 = wc[k * n_], w1 = wc[(k + 1) * n_], w2 = wc[(k + 2) * n_], w3 = wc[(k + 3) * n_];
+                const T t0 = tt[k], t1 = tt[k + 1], t2 = tt[k + 2], t3 = tt[k + 3];
+                a0 += w0 * t0;
+                a1 += w1 * t1;
+                a2 += w2 * t2;
+                a3 += w3 * t3;
             }
-            if (k < m.k) acc += wc[k * m.n] * tt[k];
-            acc += acc1;
+            for (; k < K_; ++k) a0 += wc[k * n_] * tt[k];
+            const T acc = (a0 + a1) + (a2 + a3);
             const T vr = vb[r];
             const T y = m.mode ? bbar[r] + (vr - acc) : bbar[r] + acc;
             const T z = xg[rlv[r]];
@@ -534,11 +555,15 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             p3 += double(y) * double(y);
             p4 += double(lnew) * double(lnew);
         }
-        p0 = wave_total(p0);
-        p1 = wave_total(p1);
-        p2 = wave_total(p2);
-        p3 = wave_total(p3);
-        p4 = wave_total(p4);
+        {
+            double pq[5] = {p0, p1, p2, p3, p4};
+            wave_total5(pq);
+            p0 = pq[0];
+            p1 = pq[1];
+            p2 = pq[2];
+            p3 = pq[3];
+            p4 = pq[4];
+        }
         if (lane == 0) {
             red[wv * 8 + 0] = p0;
             red[wv * 8 + 1] = p1;
@@ -613,9 +638,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         a.st->dres = a.rho * sqrt(d[1]);
         a.st->eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
         a.st->eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
-        if (PROF && a.prof)
-            for (int i = 0; i < 8; ++i) a.prof[i] = double(tprof[i]);
     }
+    if (PROF && a.prof && tid == 0)
+        for (int i = 0; i < 8; ++i) a.prof[blockIdx.x * 8 + i] = double(tprof[i]);
 }
 
 // Before every sweep launch, on the same stream: every exchange word empty,

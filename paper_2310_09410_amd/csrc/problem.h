@@ -37,7 +37,7 @@ struct ldopf_problem {
     uint64_t spin_limit = 0;
 
     DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart, gpart, prof;
-    double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::vector<double> phase_ms;  // [parts][8] per-phase ms of the last profiled solve
     double tick_ms = 1e-5;  // wall-clock tick in ms
     DevBuf<int32_t> ns, ms, rank_d, flags;
     DevBuf<int64_t> a_off, row_off, loc_off, basis_off;

@@ -178,9 +178,11 @@ class Problem:
                                            bb.shape[0], _ptr(rk, C.c_int32), rk.shape[0]), "ldopf_get_operators")
         return ab, bb, rk
 
-    def get_phase_times(self) -> np.ndarray:
+    def get_phase_times(self, part: int = 0) -> np.ndarray:
+        """Per-phase ms of workgroup `part` in the last profiled solve."""
         ms = np.zeros(8)
-        _check(N.lib().ldopf_get_phase_times(self.h, _ptr(ms, C.c_double)), "ldopf_get_phase_times")
+        _check(N.lib().ldopf_get_phase_times_part(self.h, int(part), _ptr(ms, C.c_double)),
+               "ldopf_get_phase_times_part")
         return ms
 
     def objective(self) -> float:
