@@ -201,6 +201,7 @@ template <typename T, bool PROF>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int ok_lds;
+    __shared__ int test_lds;  // 1 stop, 2 converged, 4 non-finite: the last test
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const PartInfo pi = a.parts[blockIdx.x];
     const LdsLayout L = lds_layout(sizeof(T), uint32_t(pi.w_words), uint32_t(pi.n_row), uint32_t(pi.n_tk),
@@ -414,28 +415,32 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         for (int q = 0; q < 5; ++q) v[q] = grp_in ? await_word(base + q * kGroup + lane, w2[q], limit, &ok_lds) : 0.0;
 #pragma unroll
         for (int q = 0; q < 5; ++q) v[q] = group_sum(v[q], kGroup);
-        if (lane == 0)
+        // the test itself, once per workgroup (lane 0 of wave tw)
+        if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) tot[q] = v[q];
-    };
-    // the test of one sweep from the totals in LDS (after a block barrier)
-    auto decide = [&](int64_t sweep) -> bool {
-        ok = ok_lds != 0;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) d[q] = tot[q];
-        const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
-        const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
-        const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
-        if (ok && blockIdx.x == 0 && tid == 0 && sweep <= a.hist_cap) {
-            double* h = a.hist + (sweep - 1) * 4;
-            h[0] = pres;
-            h[1] = dres;
-            h[2] = eps_p;
-            h[3] = eps_d;
+            const double pres = sqrt(v[0]), dres = a.rho * sqrt(v[1]);
+            const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(v[2]), sqrt(v[3]));
+            const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(v[4]);
+            const int nf = !isfinite(v[0] + v[1] + v[2] + v[3] + v[4]);
+            const int cv = pres <= eps_p && dres <= eps_d;
+            test_lds = ((nf || (a.check && cv)) ? 1 : 0) | (cv ? 2 : 0) | (nf ? 4 : 0);
+            if (blockIdx.x == 0 && sweep <= a.hist_cap && ok_lds) {
+                double* h = a.hist + (sweep - 1) * 4;
+                h[0] = pres;
+                h[1] = dres;
+                h[2] = eps_p;
+                h[3] = eps_d;
+            }
         }
-        nonfinite = !isfinite(d[0] + d[1] + d[2] + d[3] + d[4]);
-        converged = pres <= eps_p && dres <= eps_d;
-        return nonfinite || (a.check && converged);
+    };
+    // the outcome of that test, for every thread (after a block barrier)
+    auto decide = [&]() -> bool {
+        ok = ok_lds != 0;
+        const int f = test_lds;
+        converged = (f & 2) != 0;
+        nonfinite = (f & 4) != 0;
+        return (f & 1) != 0;
     };
 
     bool stopped = false;
@@ -463,7 +468,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             break;
         }
         if (done >= 3) {
-            if (decide(done - 2)) {
+            if (decide()) {
                 // x_s, lambda of sweep done - 2 are intact (this sweep's
                 // local update has not run), and so is its x (buffer % 4)
                 result = done - 2;
@@ -615,7 +620,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             }
             __syncthreads();
             result = k;
-            if (decide(k) || !ok) break;
+            if (decide() || !ok) break;
             __syncthreads();  // tot is rewritten for the next sweep
         }
     }
@@ -631,6 +636,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             if (a.var_writer[pi.var_begin + v]) a.x[a.var_gid[pi.var_begin + v]] = double(XL(fx)[v]);
     if (tid == 0 && (!ok || nonfinite)) atomicOr(&a.st->flags, (ok ? 0 : 1) | (nonfinite ? 2 : 0));
     if (blockIdx.x == 0 && tid == 0) {
+        if (result > 0)
+            for (int q = 0; q < 5; ++q) d[q] = tot[q];
         a.st->iters = result;
         a.st->computed = done;
         a.st->converged = converged;
