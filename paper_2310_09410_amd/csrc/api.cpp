@@ -298,7 +298,7 @@ int problem_finish(ldopf_problem& h, ldopf_status* status) {
     }
     h.hist_len = h.opts.history ? std::min<int64_t>(st.iters, int64_t(h.hist.count / 4)) : 0;
     if (st.iters > 0) h.have_x = true;
-    if (st.flags & 1) fail(LDOPF_DEVICE_ERROR, "grid barrier wait timed out in the sweep kernel");
+    if (st.flags & 1) fail(LDOPF_DEVICE_ERROR, "a cross-workgroup wait timed out in the sweep kernel");
     int code = LDOPF_OK;
     if (st.flags & 2) {
         code = LDOPF_NUMERICAL;

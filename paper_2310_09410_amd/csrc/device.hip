@@ -389,6 +389,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             for (int q = 0; q < 5; ++q) st_empty(base + q * P + member);
     };
     uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t tw_prof = 0;  // wave tw's time in the test's totals, inside phase 0
     uint64_t tlast = 0;
     auto stamp = [&](int ph) {
         if (PROF && tid == 0) {
@@ -453,7 +454,11 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         T* xg = XL(int((done + 1) & 3));
         // the test of sweep done - 2 overlaps this global update: wave tw
         // forms the totals now, every thread reads them after the barrier
-        if (wv == tw && done >= 3) totals(done - 2);
+        if (wv == tw && done >= 3) {
+            const uint64_t t0 = PROF ? wall_clock64() : 0;
+            totals(done - 2);
+            if (PROF && lane == 0) tw_prof += wall_clock64() - t0;
+        }
         // closed_1: clipped average of the copies
         for (int v = tid; tid < g_threads && v < V; v += g_threads) {
             const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
@@ -462,6 +467,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             xv = xv > vhi[v] ? vhi[v] : xv;
             xg[v] = xv;
         }
+        if (PROF && tid == 0) tprof[7] += wall_clock64() - tlast;  // the workgroup's own global update, inside phase 0
         __syncthreads();
         if (ok_lds == 0) {
             ok = false;
@@ -647,7 +653,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         a.st->eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
     }
     if (PROF && a.prof && tid == 0)
-        for (int i = 0; i < 8; ++i) a.prof[blockIdx.x * 8 + i] = double(tprof[i]);
+        for (int i = 0; i < 8; ++i)
+            if (i != 6) a.prof[blockIdx.x * 8 + i] = double(tprof[i]);
+    if (PROF && a.prof && wv == tw && lane == 0) a.prof[blockIdx.x * 8 + 6] = double(tw_prof);
 }
 
 // Before every sweep launch, on the same stream: every exchange word empty,
