@@ -261,12 +261,12 @@ LDOPF_API int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t 
                                   double* bbar, int64_t cap_bbar, int32_t* rank, int64_t cap_rank);
 /* Per-phase device time of the last solve with options.profile = 1, in ms,
  * measured by workgroup 0 with the wall clock: [0] global update, with the
- * wait for the neighbours' partial sums and the termination test of an
- * earlier sweep, [1] gather of B_s x + lambda/rho, [2] t = W v, [3] local
- * and dual update with residual sums, [4] partial sums and publication,
- * [5] end of the sweep; inside [0]: [6] the reader wave's wait for and sum
- * of the residual group sums, [7] the workgroup's own global update before
- * its barrier. Zeros when profiling was off. */
+ * wait for the neighbours' partial sums, [1] gather of B_s x + lambda/rho,
+ * [2] t = W v, alongside the termination test of an earlier sweep, [3] local
+ * and dual update with residual row sums, [4] partial sums and publication,
+ * [5] end of the sweep; [6] the reader wave's termination test (the grid
+ * totals from the group sums, inside [2]), [7] the workgroup's own global
+ * update before its barrier (inside [0]). Zeros when profiling was off. */
 LDOPF_API int ldopf_get_phase_times(const ldopf_problem* h, double ms[8]);
 /* The same for workgroup `part` (0 <= part < ldopf_sizes.n_parts). */
 LDOPF_API int ldopf_get_phase_times_part(const ldopf_problem* h, int32_t part, double ms[8]);

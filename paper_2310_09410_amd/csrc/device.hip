@@ -51,15 +51,17 @@ constexpr int kDppXor2 = 0x4E;
 constexpr int kDppHalfMirror = 0x141;
 constexpr int kDppMirror = 0x140;
 
+// Every source lane of these patterns lies inside the row, so every lane is
+// written and no fallback value is needed.
 template <int CTRL>
 __device__ inline double dpp_move(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ inline float dpp_move(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
 // Sum over aligned groups of g lanes (g = 1, 2, 4, 8, 16); every lane of a
@@ -78,12 +80,10 @@ __device__ inline double read_lane(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// Sums over the 64 lanes of a wave of five values, without LDS traffic: row
-// sums by DPP, then the four row sums in a fixed order. Results are
-// wave-uniform and the same on every wave given the same inputs. The steps
-// run across the five values so that their DPP chains overlap. Needs every
-// lane of the wave active.
-__device__ inline void wave_total5(double* v) {
+// Sums over each row of 16 lanes of five values (every lane of the row ends
+// with the row's sums); the steps run across the five values so that their
+// DPP chains overlap. Needs every lane of the wave active.
+__device__ inline void row_sum5(double* v) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) v[q] += dpp_move<kDppXor1>(v[q]);
 #pragma unroll
@@ -92,8 +92,6 @@ __device__ inline void wave_total5(double* v) {
     for (int q = 0; q < 5; ++q) v[q] += dpp_move<kDppHalfMirror>(v[q]);
 #pragma unroll
     for (int q = 0; q < 5; ++q) v[q] += dpp_move<kDppMirror>(v[q]);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) v[q] = (read_lane(v[q], 0) + read_lane(v[q], 16)) + (read_lane(v[q], 32) + read_lane(v[q], 48));
 }
 
 __device__ inline void st_agent(double* p, double v) {
@@ -231,7 +229,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     uint16_t* tks = reinterpret_cast<uint16_t*>(smem + L.tk_sub);
     SubLds* meta = reinterpret_cast<SubLds*>(smem + L.meta);
     double* red = reinterpret_cast<double*>(smem + L.red);
-    double* tot = red + 8 * nw;
+    double* tot = red + 32 * nw;  // after the row sums [waves][4][8]
 
     const T rho = T(a.rho);
     const T irho = T(1.0 / a.rho);
@@ -278,11 +276,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     __syncthreads();
 
     // The last wave reads the residual sums of all parts back and runs the
-    // test; it takes no part in the global update and the boundary exchange,
-    // whose loads would otherwise wait (in-order vmcnt) on its loads in
-    // flight. With a single wave, that wave does everything.
+    // test (while the other waves form t = W v); it holds no rows and takes
+    // no part in the global update and the boundary exchange, whose loads
+    // would otherwise wait (in-order vmcnt) on its loads in flight. The other
+    // waves leave it their residual sums per row of 16 lanes. With a single
+    // wave, that wave does everything.
     const int tw = nw - 1;
     const int g_threads = nw > 1 ? nt - 64 : nt;
+    const int n_work = g_threads >> 6;  // waves that hold rows
 
     // publish a boundary variable's partial sum to every other owner
     auto publish = [&](T* buf, int v, T acc) {
@@ -343,53 +344,52 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     }
     __syncthreads();
 
-    const int GA = task_lanes(TK, nt);
+    const int GA = task_lanes(TK, g_threads);
     // Residual sums, reduced in two levels by wave tw. Level 1: every part's
     // 5 sums of a sweep (ring entry [8][P], quantity-major), read only by its
     // group leader, the first of each kGroup consecutive parts, which adds
-    // its members' sums (lane l stands for member l) and publishes them
-    // (level 2, ring entry [8][kGroup]); every part then reads the group
-    // sums (lane l stands for group l) and runs the test. Both sums use the
-    // same lane order everywhere, so every part takes the same decision.
+    // its members' sums and publishes them (level 2, ring entry [8][kGroup]);
+    // every part then reads the group sums and runs the test. Lanes hold the
+    // five quantities transposed: lane 16q + i holds quantity q (q < 4) of
+    // member (group) i in word A, and lanes i < 16 hold quantity 4 in word B,
+    // so that two 16-lane sums serve all five. Every part adds in the same
+    // lane order, so every part takes the same decision.
+    static_assert(kGroup == 16, "one lane row per group");
     const bool leader = blockIdx.x % kGroup == 0;
     const unsigned grp = blockIdx.x / kGroup, ngroups = (P + kGroup - 1) / kGroup;
-    const unsigned member = blockIdx.x + unsigned(lane);
-    const bool mem_in = lane < kGroup && member < P;
-    const bool grp_in = unsigned(lane) < ngroups;
-    unsigned long long w1[5], w2[5];
+    const int qa = lane >> 4, gi = lane & 15;
+    const unsigned member = blockIdx.x + unsigned(gi);
+    const bool mem_a = member < P, mem_b = mem_a && lane < 16;
+    const bool grp_a = unsigned(gi) < ngroups, grp_b = grp_a && lane < 16;
+    unsigned long long w1a = 0, w1b = 0, w2a = 0, w2b = 0;
     auto ring1 = [&](int64_t sweep) -> double* { return a.rpart + int64_t(sweep & (kRing - 1)) * P * 8; };
     auto ring2 = [&](int64_t sweep) -> double* { return a.gpart + int64_t(sweep & (kRing - 1)) * 8 * kGroup; };
     auto issue_members = [&](int64_t sweep) {
-        const double* base = ring1(sweep);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) w1[q] = mem_in ? ld_word(base + q * P + member) : 0ull;
+        const double* base = ring1(sweep) + member;
+        w1a = mem_a ? ld_word(base + qa * P) : 0ull;
+        w1b = mem_b ? ld_word(base + 4 * P) : 0ull;
     };
     auto issue_groups = [&](int64_t sweep) {
-        const double* base = ring2(sweep);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) w2[q] = grp_in ? ld_word(base + q * kGroup + lane) : 0ull;
+        const double* base = ring2(sweep) + gi;
+        w2a = grp_a ? ld_word(base + qa * kGroup) : 0ull;
+        w2b = grp_b ? ld_word(base + 4 * kGroup) : 0ull;
     };
     // leader: its members' sums of `sweep` added and published; the members'
     // words emptied (the leader is their only reader)
     auto group_sums = [&](int64_t sweep) {
-        double* base = ring1(sweep);
-        double v[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            v[q] = mem_in ? await_word(base + q * P + member, w1[q], limit, &ok_lds) : 0.0;
-            v[q] = group_sum(v[q], kGroup);
-        }
-        double* g = ring2(sweep);
-        if (lane < 5) {
-            const double t = lane == 0 ? v[0] : (lane == 1 ? v[1] : (lane == 2 ? v[2] : (lane == 3 ? v[3] : v[4])));
-            st_agent(g + lane * kGroup + grp, t);
-        }
-        if (mem_in)
-#pragma unroll
-            for (int q = 0; q < 5; ++q) st_empty(base + q * P + member);
+        double* base = ring1(sweep) + member;
+        double va = mem_a ? await_word(base + qa * P, w1a, limit, &ok_lds) : 0.0;
+        double vb = mem_b ? await_word(base + 4 * P, w1b, limit, &ok_lds) : 0.0;
+        va = group_sum(va, kGroup);
+        vb = group_sum(vb, kGroup);
+        double* g = ring2(sweep) + grp;
+        if (gi == 0) st_agent(g + qa * kGroup, va);
+        if (lane == 0) st_agent(g + 4 * kGroup, vb);
+        if (mem_a) st_empty(base + qa * P);
+        if (mem_b) st_empty(base + 4 * P);
     };
     uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    uint64_t tw_prof = 0;  // wave tw's time in the test's totals, inside phase 0
+    uint64_t tw_prof = 0;  // wave tw's time in the test's totals, inside phase 2
     uint64_t tlast = 0;
     auto stamp = [&](int ph) {
         if (PROF && tid == 0) {
@@ -410,20 +410,25 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     // wave tw: the grid-wide sums of one sweep from the group sums (loads
     // issued by issue_groups), into LDS for every thread
     auto totals = [&](int64_t sweep) {
-        const double* base = ring2(sweep);
-        double v[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) v[q] = grp_in ? await_word(base + q * kGroup + lane, w2[q], limit, &ok_lds) : 0.0;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) v[q] = group_sum(v[q], kGroup);
-        // the test itself, once per workgroup (lane 0 of wave tw)
+        const double* base = ring2(sweep) + gi;
+        double va = grp_a ? await_word(base + qa * kGroup, w2a, limit, &ok_lds) : 0.0;
+        double vb = grp_b ? await_word(base + 4 * kGroup, w2b, limit, &ok_lds) : 0.0;
+        va = group_sum(va, kGroup);
+        vb = group_sum(vb, kGroup);
+        // the grid totals: quantity q < 4 in lane 16q of A, quantity 4 in
+        // lane 0 of B; their square roots taken lane-parallel
+        if (gi == 0) tot[qa] = va;
+        if (lane == 0) tot[4] = vb;
+        const double ra = sqrt(va), rb = sqrt(vb);
+        const double r0 = read_lane(ra, 0), r1 = read_lane(ra, 16), r2 = read_lane(ra, 32), r3 = read_lane(ra, 48);
+        const double r4 = read_lane(rb, 0);
+        // the test itself, once per workgroup (lane 0 of wave tw); the sums
+        // are of squares, so a non-finite sum shows in its square root
         if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) tot[q] = v[q];
-            const double pres = sqrt(v[0]), dres = a.rho * sqrt(v[1]);
-            const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(v[2]), sqrt(v[3]));
-            const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(v[4]);
-            const int nf = !isfinite(v[0] + v[1] + v[2] + v[3] + v[4]);
+            const double pres = r0, dres = a.rho * r1;
+            const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(r2, r3);
+            const double eps_d = sq * a.eps_abs + a.eps_rel * r4;
+            const int nf = !isfinite(r0 + r1 + r2 + r3 + r4);
             const int cv = pres <= eps_p && dres <= eps_d;
             test_lds = ((nf || (a.check && cv)) ? 1 : 0) | (cv ? 2 : 0) | (nf ? 4 : 0);
             if (blockIdx.x == 0 && sweep <= a.hist_cap && ok_lds) {
@@ -452,13 +457,6 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         T* bcur = a.bpart + int64_t(bp) * ns;
         T* bnx = a.bpart + int64_t(bp ^ 1) * ns;
         T* xg = XL(int((done + 1) & 3));
-        // the test of sweep done - 2 overlaps this global update: wave tw
-        // forms the totals now, every thread reads them after the barrier
-        if (wv == tw && done >= 3) {
-            const uint64_t t0 = PROF ? wall_clock64() : 0;
-            totals(done - 2);
-            if (PROF && lane == 0) tw_prof += wall_clock64() - t0;
-        }
         // closed_1: clipped average of the copies
         for (int v = tid; tid < g_threads && v < V; v += g_threads) {
             const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
@@ -473,35 +471,31 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             ok = false;
             break;
         }
-        if (done >= 3) {
-            if (decide()) {
-                // x_s, lambda of sweep done - 2 are intact (this sweep's
-                // local update has not run), and so is its x (buffer % 4)
-                result = done - 2;
-                stopped = true;
-                break;
-            }
-            // every part has read the group sums of sweep done - 5 (each part
-            // tests sweep j before it publishes sweep j + 3)
-            if (wv == tw && leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
-        }
         stamp(0);
         // v = B_s x + lambda_s / rho
         const T* lc = LAM(cur);
-        for (int r = tid; r < R; r += nt) vb[r] = xg[rlv[r]] + lc[r] * irho;
+        for (int r = tid; tid < g_threads && r < R; r += g_threads) vb[r] = xg[rlv[r]] + lc[r] * irho;
         __syncthreads();
         stamp(1);
-        // wave tw: its earlier stores complete before it stores again (they
-        // were issued a phase or more ago); then the loads of this sweep:
-        // the leader's members' sums of the previous sweep, and the group
-        // sums of sweep done - 1 for the test after this sweep
         if (wv == tw) {
+            // the test of sweep done - 2, while the other waves form t;
+            // its stores of the last phase completed first (issued a phase
+            // or more ago), then the load of the leader's members' sums of
+            // the previous sweep
             __builtin_amdgcn_s_waitcnt(0);
+            if (done >= 3) {
+                const uint64_t t0 = PROF ? wall_clock64() : 0;
+                totals(done - 2);
+                if (PROF && lane == 0) tw_prof += wall_clock64() - t0;
+                // every part has read the group sums of sweep done - 5:
+                // their sums of sweep done - 2 are all in, and each part
+                // tests sweep j before it publishes sweep j + 3
+                if (leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
+            }
             if (leader && done >= 1) issue_members(done);
-            if (done >= 2) issue_groups(done - 1);
         }
         // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
-        for (int base = 0; base < TK * GA; base += nt) {
+        for (int base = 0; tid < g_threads && base < TK * GA; base += g_threads) {
             const int q0 = base + tid;
             const int task = q0 / GA, sub = q0 - task * GA;
             T acc = T(0);
@@ -527,66 +521,79 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             if (task < TK && sub == 0) tb[task] = acc;
         }
         __syncthreads();
+        if (done >= 3) {
+            if (ok_lds == 0) {
+                ok = false;
+                break;
+            }
+            if (decide()) {
+                // x_s, lambda of sweep done - 2 are intact (this sweep's
+                // local update has not run), and so is its x (buffer % 4)
+                result = done - 2;
+                stopped = true;
+                break;
+            }
+        }
         stamp(2);
         // closed_2 in rank form, then ADMM-3; residual sums in FP64
-        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
         const T* xc = XS(cur);
         T* xn = XS(nx);
         T* ln = LAM(nx);
-        for (int r = tid; r < R; r += nt) {
-            const SubLds m = meta[rsub[r]];
-            const int j = r - m.row0;
-            const T* wc = W + m.w0 + j;
-            const T* tt = tb + m.t0;
-            // four products per step, their eight loads issued together
-            const int n_ = m.n, K_ = m.k;
-            T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-            int k = 0;
-            for (; k + 4 <= K_; k += 4) {
-                const T w0 = wc[k * n_], w1 = wc[(k + 1) * n_], w2 = wc[(k + 2) * n_], w3 = wc[(k + 3) * n_];
-                const T t0 = tt[k], t1 = tt[k + 1], t2 = tt[k + 2], t3 = tt[k + 3];
-                a0 += w0 * t0;
-                a1 += w1 * t1;
-                a2 += w2 * t2;
-                a3 += w3 * t3;
+        if (tid < g_threads) {
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
+            for (int r = tid; r < R; r += g_threads) {
+                const SubLds m = meta[rsub[r]];
+                const int j = r - m.row0;
+                const T* wc = W + m.w0 + j;
+                const T* tt = tb + m.t0;
+                // four products per step, their eight loads issued together
+                const int n_ = m.n, K_ = m.k;
+                T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+                int k = 0;
+                for (; k + 4 <= K_; k += 4) {
+                    const T w0 = wc[k * n_], w1 = wc[(k + 1) * n_], w2 = wc[(k + 2) * n_], w3 = wc[(k + 3) * n_];
+                    const T t0 = tt[k], t1 = tt[k + 1], t2 = tt[k + 2], t3 = tt[k + 3];
+                    a0 += w0 * t0;
+                    a1 += w1 * t1;
+                    a2 += w2 * t2;
+                    a3 += w3 * t3;
+                }
+                for (; k < K_; ++k) a0 += wc[k * n_] * tt[k];
+                const T acc = (a0 + a1) + (a2 + a3);
+                const T vr = vb[r];
+                const T y = m.mode ? bbar[r] + (vr - acc) : bbar[r] + acc;
+                const T z = xg[rlv[r]];
+                const T lnew = lc[r] + rho * (z - y);
+                xn[r] = y;
+                ln[r] = lnew;
+                const double dz = double(z) - double(y);
+                const double dx = double(y) - double(xc[r]);
+                p0 += dz * dz;
+                p1 += dx * dx;
+                p2 += double(z) * double(z);
+                p3 += double(y) * double(y);
+                p4 += double(lnew) * double(lnew);
             }
-            for (; k < K_; ++k) a0 += wc[k * n_] * tt[k];
-            const T acc = (a0 + a1) + (a2 + a3);
-            const T vr = vb[r];
-            const T y = m.mode ? bbar[r] + (vr - acc) : bbar[r] + acc;
-            const T z = xg[rlv[r]];
-            const T lnew = lc[r] + rho * (z - y);
-            xn[r] = y;
-            ln[r] = lnew;
-            const double dz = double(z) - double(y);
-            const double dx = double(y) - double(xc[r]);
-            p0 += dz * dz;
-            p1 += dx * dx;
-            p2 += double(z) * double(z);
-            p3 += double(y) * double(y);
-            p4 += double(lnew) * double(lnew);
-        }
-        {
+            // each row of 16 lanes sums its values; its first lane leaves
+            // them for wave tw
             double pq[5] = {p0, p1, p2, p3, p4};
-            wave_total5(pq);
-            p0 = pq[0];
-            p1 = pq[1];
-            p2 = pq[2];
-            p3 = pq[3];
-            p4 = pq[4];
+            row_sum5(pq);
+            if ((lane & 15) == 0) {
+                double* o = red + (wv * 4 + (lane >> 4)) * 8;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) o[q] = pq[q];
+            }
+            // this sweep's emptied exchange words are stored before any
+            // partial sum of this sweep is published
+            __builtin_amdgcn_s_waitcnt(0);
         }
-        if (lane == 0) {
-            red[wv * 8 + 0] = p0;
-            red[wv * 8 + 1] = p1;
-            red[wv * 8 + 2] = p2;
-            red[wv * 8 + 3] = p3;
-            red[wv * 8 + 4] = p4;
-        }
-        // this sweep's emptied exchange words are stored before any partial
-        // sum of this sweep is published
-        if (wv != tw || nw == 1) __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         stamp(3);
+        // wave tw's loads of the t phase have long returned (the other waves
+        // have nothing outstanding): waiting for them here, on every wave's
+        // path and before any store of this phase, keeps the later waits on
+        // them (group sums, totals) from also waiting for those stores
+        __builtin_amdgcn_s_waitcnt(0);
         // partial sums for the next global update; publish boundary slots
         for (int v = tid; tid < g_threads && v < V; v += g_threads) {
             T acc = T(0);
@@ -598,12 +605,21 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             publish(bnx, v, acc);
         }
         if (wv == tw) {
-            if (leader && done >= 1) group_sums(done);
-            if (lane < 5) {
-                double acc = 0.0;
-                for (int w = 0; w < nw; ++w) acc += red[w * 8 + lane];
-                st_agent(ring1(done + 1) + lane * P + blockIdx.x, acc);
+            // the group sums of sweep done - 1 for the next test, loaded
+            // before this phase's stores (a sweep after the leaders stored
+            // them, and a sweep before they are needed)
+            if (done >= 2) issue_groups(done - 1);
+            // this part's sums of the sweep from the row sums of the work
+            // waves: lane 8q + j adds rows j, j + 8, ... of quantity q, then
+            // the 8 lanes of q are added
+            double sq_ = 0.0;
+            if (lane < 40) {
+                const int q = lane >> 3;
+                for (int i = lane & 7; i < 4 * n_work; i += 8) sq_ += red[i * 8 + q];
             }
+            sq_ = group_sum(sq_, 8);
+            if (leader && done >= 1) group_sums(done);
+            if (lane < 40 && (lane & 7) == 0) st_agent(ring1(done + 1) + (lane >> 3) * P + blockIdx.x, sq_);
         }
         stamp(4);
         ++done;
