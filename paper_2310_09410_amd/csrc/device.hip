@@ -276,7 +276,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     __syncthreads();
 
     // The last wave reads the residual sums of all parts back and runs the
-    // test (while the other waves form t = W v); it holds no rows and takes
+    // test (during the global update); it holds no rows and takes
     // no part in the global update and the boundary exchange, whose loads
     // would otherwise wait (in-order vmcnt) on its loads in flight. The other
     // waves leave it their residual sums per row of 16 lanes. With a single
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         if (mem_b) st_empty(base + 4 * P);
     };
     uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    uint64_t tw_prof = 0;  // wave tw's time in the test's totals, inside phase 2
+    uint64_t tw_prof = 0;  // wave tw's time in the test's totals, inside phase 0
     uint64_t tlast = 0;
     auto stamp = [&](int ph) {
         if (PROF && tid == 0) {
@@ -457,6 +457,18 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         T* bcur = a.bpart + int64_t(bp) * ns;
         T* bnx = a.bpart + int64_t(bp ^ 1) * ns;
         T* xg = XL(int((done + 1) & 3));
+        // the test of sweep done - 2 overlaps this global update: wave tw
+        // forms the totals now, every thread reads the outcome after the
+        // barrier
+        if (wv == tw && done >= 3) {
+            const uint64_t t0 = PROF ? wall_clock64() : 0;
+            totals(done - 2);
+            if (PROF && lane == 0) tw_prof += wall_clock64() - t0;
+            // every part has read the group sums of sweep done - 5: their
+            // sums of sweep done - 2 are all in, and each part tests sweep j
+            // before it publishes sweep j + 3
+            if (leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
+        }
         // closed_1: clipped average of the copies
         for (int v = tid; tid < g_threads && v < V; v += g_threads) {
             const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
@@ -471,6 +483,13 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             ok = false;
             break;
         }
+        if (done >= 3 && decide()) {
+            // x_s, lambda of sweep done - 2 are intact (this sweep's local
+            // update has not run), and so is its x (buffer % 4)
+            result = done - 2;
+            stopped = true;
+            break;
+        }
         stamp(0);
         // v = B_s x + lambda_s / rho
         const T* lc = LAM(cur);
@@ -478,21 +497,13 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         __syncthreads();
         stamp(1);
         if (wv == tw) {
-            // the test of sweep done - 2, while the other waves form t;
-            // its stores of the last phase completed first (issued a phase
-            // or more ago), then the load of the leader's members' sums of
-            // the previous sweep
+            // its stores of the last phase complete first (issued a phase or
+            // more ago); then the loads of this sweep: the leader's members'
+            // sums of the previous sweep, and the group sums of sweep
+            // done - 1 for the next test
             __builtin_amdgcn_s_waitcnt(0);
-            if (done >= 3) {
-                const uint64_t t0 = PROF ? wall_clock64() : 0;
-                totals(done - 2);
-                if (PROF && lane == 0) tw_prof += wall_clock64() - t0;
-                // every part has read the group sums of sweep done - 5:
-                // their sums of sweep done - 2 are all in, and each part
-                // tests sweep j before it publishes sweep j + 3
-                if (leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
-            }
             if (leader && done >= 1) issue_members(done);
+            if (done >= 2) issue_groups(done - 1);
         }
         // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
         for (int base = 0; tid < g_threads && base < TK * GA; base += g_threads) {
@@ -521,19 +532,6 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             if (task < TK && sub == 0) tb[task] = acc;
         }
         __syncthreads();
-        if (done >= 3) {
-            if (ok_lds == 0) {
-                ok = false;
-                break;
-            }
-            if (decide()) {
-                // x_s, lambda of sweep done - 2 are intact (this sweep's
-                // local update has not run), and so is its x (buffer % 4)
-                result = done - 2;
-                stopped = true;
-                break;
-            }
-        }
         stamp(2);
         // closed_2 in rank form, then ADMM-3; residual sums in FP64
         const T* xc = XS(cur);
@@ -605,10 +603,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             publish(bnx, v, acc);
         }
         if (wv == tw) {
-            // the group sums of sweep done - 1 for the next test, loaded
-            // before this phase's stores (a sweep after the leaders stored
-            // them, and a sweep before they are needed)
-            if (done >= 2) issue_groups(done - 1);
+            // group-sum words of sweep done - 1 that were still empty when
+            // loaded in the t phase are loaded again, before this phase's
+            // stores (the wait above made their values known)
+            if (done >= 2) {
+                const double* base = ring2(done - 1) + gi;
+                if (grp_a && w2a == Word<double>::kEmpty) w2a = ld_word(base + qa * kGroup);
+                if (grp_b && w2b == Word<double>::kEmpty) w2b = ld_word(base + 4 * kGroup);
+            }
             // this part's sums of the sweep from the row sums of the work
             // waves: lane 8q + j adds rows j, j + 8, ... of quantity q, then
             // the 8 lanes of q are added
