@@ -174,15 +174,16 @@ template <typename T>
 __device__ inline T await_word(const T* p, typename Word<T>::U u, uint64_t limit, int* ok) {
     if (u != Word<T>::kEmpty) return Word<T>::value(u);
     const uint64_t t0 = wall_clock64();
-    while (u == Word<T>::kEmpty) {
-        __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t0 > limit) {
+    // re-read back to back; the clock (a scalar memory read) only every
+    // 16th time, so that a word is seen about one load after it lands
+    for (uint32_t n = 1;; ++n) {
+        u = ld_word(p);
+        if (u != Word<T>::kEmpty) return Word<T>::value(u);
+        if ((n & 15u) == 0 && wall_clock64() - t0 > limit) {
             *ok = 0;
             return T(0);
         }
-        u = ld_word(p);
     }
-    return Word<T>::value(u);
 }
 
 // Lanes per (subsystem, basis row) task of t = W v: as many as the
