@@ -149,7 +149,8 @@ typedef struct ldopf_options {
     int32_t check_termination; /* 1 (default): stop at the test; 0: run exactly max_iter sweeps */
     int32_t history;         /* 1 (default): record pres, dres, eps_prim, eps_dual per sweep */
     int32_t rows_per_part;   /* tuning: local copies per workgroup; 0 = automatic */
-    int32_t block_threads;   /* tuning: threads per workgroup (64..1024, multiple of 64); 0 = automatic */
+    int32_t block_threads;   /* tuning: threads per workgroup (128..1024, multiple of 64: row waves plus the
+                                wave that runs the termination test); 0 = automatic */
     int32_t profile;         /* 1: record per-phase device time of the sweep (ldopf_get_phase_times); default 0 */
     int32_t reserved[5];     /* must be zero */
 } ldopf_options;

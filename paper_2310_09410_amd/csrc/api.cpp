@@ -38,8 +38,8 @@ void check_options(const ldopf_options& o) {
     if (o.history != 0 && o.history != 1) fail(LDOPF_INVALID_ARGUMENT, "history must be 0 or 1");
     if (o.profile != 0 && o.profile != 1) fail(LDOPF_INVALID_ARGUMENT, "profile must be 0 or 1");
     if (o.rows_per_part < 0) fail(LDOPF_INVALID_ARGUMENT, "rows_per_part must be >= 0");
-    if (o.block_threads != 0 && (o.block_threads < 64 || o.block_threads > 1024 || o.block_threads % 64))
-        fail(LDOPF_INVALID_ARGUMENT, "block_threads must be 0 or a multiple of 64 in [64, 1024]");
+    if (o.block_threads != 0 && (o.block_threads < 128 || o.block_threads > 1024 || o.block_threads % 64))
+        fail(LDOPF_INVALID_ARGUMENT, "block_threads must be 0 or a multiple of 64 in [128, 1024]");
     for (int r : o.reserved)
         if (r != 0) fail(LDOPF_INVALID_ARGUMENT, "reserved option fields must be zero");
 }

@@ -280,10 +280,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     // test (during the global update); it holds no rows and takes
     // no part in the global update and the boundary exchange, whose loads
     // would otherwise wait (in-order vmcnt) on its loads in flight. The other
-    // waves leave it their residual sums per row of 16 lanes. With a single
-    // wave, that wave does everything.
+    // waves leave it their residual sums per row of 16 lanes.
     const int tw = nw - 1;
-    const int g_threads = nw > 1 ? nt - 64 : nt;
+    const int g_threads = nt - 64;  // two waves at least (checked by the host)
     const int n_work = g_threads >> 6;  // waves that hold rows
 
     // publish a boundary variable's partial sum to every other owner
@@ -451,53 +450,33 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     };
 
     bool stopped = false;
-    int cur = 0;  // x_s, lambda buffer of sweep `done` (sweep k lives in buffer k % 3, its x in k % 4)
-    while (done < a.max_iter) {
-        const int nx = cur == 2 ? 0 : cur + 1;
-        const int bp = int(done & 1);  // exchange-word parity
-        T* bcur = a.bpart + int64_t(bp) * ns;
-        T* bnx = a.bpart + int64_t(bp ^ 1) * ns;
-        T* xg = XL(int((done + 1) & 3));
-        // the test of sweep done - 2 overlaps this global update: wave tw
-        // forms the totals now, every thread reads the outcome after the
-        // barrier
-        if (wv == tw && done >= 3) {
-            const uint64_t t0 = PROF ? wall_clock64() : 0;
-            totals(done - 2);
-            if (PROF && lane == 0) tw_prof += wall_clock64() - t0;
-            // every part has read the group sums of sweep done - 5: their
-            // sums of sweep done - 2 are all in, and each part tests sweep j
-            // before it publishes sweep j + 3
-            if (leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
-        }
-        // closed_1: clipped average of the copies
-        for (int v = tid; tid < g_threads && v < V; v += g_threads) {
-            const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
-            T xv = (s - crho[v]) * vcnt[v];
-            xv = xv < vlo[v] ? vlo[v] : xv;
-            xv = xv > vhi[v] ? vhi[v] : xv;
-            xg[v] = xv;
-        }
-        if (PROF && tid == 0) tprof[7] += wall_clock64() - tlast;  // the workgroup's own global update, inside phase 0
-        __syncthreads();
-        if (ok_lds == 0) {
-            ok = false;
-            break;
-        }
-        if (done >= 3 && decide()) {
-            // x_s, lambda of sweep done - 2 are intact (this sweep's local
-            // update has not run), and so is its x (buffer % 4)
-            result = done - 2;
-            stopped = true;
-            break;
-        }
-        stamp(0);
-        // v = B_s x + lambda_s / rho
-        const T* lc = LAM(cur);
-        for (int r = tid; tid < g_threads && r < R; r += g_threads) vb[r] = xg[rlv[r]] + lc[r] * irho;
-        __syncthreads();
-        stamp(1);
-        if (wv == tw) {
+    // The two roles run loops of their own (so that neither carries the
+    // other's registers), with the same barriers in the same order: B1 after
+    // the global update (where both read the outcome of the test), B2 after
+    // the gather, B3 after t = W v, B4 after the local update.
+    if (wv == tw) {
+        while (done < a.max_iter) {
+            // the test of sweep done - 2, during the global update
+            if (done >= 3) {
+                const uint64_t t0 = PROF ? wall_clock64() : 0;
+                totals(done - 2);
+                if (PROF && lane == 0) tw_prof += wall_clock64() - t0;
+                // every part has read the group sums of sweep done - 5: their
+                // sums of sweep done - 2 are all in, and each part tests
+                // sweep j before it publishes sweep j + 3
+                if (leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
+            }
+            __syncthreads();  // B1
+            if (ok_lds == 0) {
+                ok = false;
+                break;
+            }
+            if (done >= 3 && decide()) {
+                result = done - 2;
+                stopped = true;
+                break;
+            }
+            __syncthreads();  // B2
             // its stores of the last phase complete first (issued a phase or
             // more ago); then the loads of this sweep: the leader's members'
             // sums of the previous sweep, and the group sums of sweep
@@ -505,105 +484,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             __builtin_amdgcn_s_waitcnt(0);
             if (leader && done >= 1) issue_members(done);
             if (done >= 2) issue_groups(done - 1);
-        }
-        // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
-        for (int base = 0; tid < g_threads && base < TK * GA; base += g_threads) {
-            const int q0 = base + tid;
-            const int task = q0 / GA, sub = q0 - task * GA;
-            T acc = T(0);
-            if (task < TK) {
-                const SubLds m = meta[tks[task]];
-                const T* wr = W + m.w0 + (task - m.t0) * m.n;
-                const T* vv = vb + m.row0;
-                // four products per step, their eight loads issued together
-                T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-                int j = sub;
-                for (; j + 3 * GA < m.n; j += 4 * GA) {
-                    const T w0 = wr[j], w1 = wr[j + GA], w2 = wr[j + 2 * GA], w3 = wr[j + 3 * GA];
-                    const T v0 = vv[j], v1 = vv[j + GA], v2 = vv[j + 2 * GA], v3 = vv[j + 3 * GA];
-                    a0 += w0 * v0;
-                    a1 += w1 * v1;
-                    a2 += w2 * v2;
-                    a3 += w3 * v3;
-                }
-                for (; j < m.n; j += GA) a0 += wr[j] * vv[j];
-                acc = (a0 + a1) + (a2 + a3);
-            }
-            acc = group_sum(acc, GA);
-            if (task < TK && sub == 0) tb[task] = acc;
-        }
-        __syncthreads();
-        stamp(2);
-        // closed_2 in rank form, then ADMM-3; residual sums in FP64
-        const T* xc = XS(cur);
-        T* xn = XS(nx);
-        T* ln = LAM(nx);
-        if (tid < g_threads) {
-            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
-            for (int r = tid; r < R; r += g_threads) {
-                const SubLds m = meta[rsub[r]];
-                const int j = r - m.row0;
-                const T* wc = W + m.w0 + j;
-                const T* tt = tb + m.t0;
-                // four products per step, their eight loads issued together
-                const int n_ = m.n, K_ = m.k;
-                T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-                int k = 0;
-                for (; k + 4 <= K_; k += 4) {
-                    const T w0 = wc[k * n_], w1 = wc[(k + 1) * n_], w2 = wc[(k + 2) * n_], w3 = wc[(k + 3) * n_];
-                    const T t0 = tt[k], t1 = tt[k + 1], t2 = tt[k + 2], t3 = tt[k + 3];
-                    a0 += w0 * t0;
-                    a1 += w1 * t1;
-                    a2 += w2 * t2;
-                    a3 += w3 * t3;
-                }
-                for (; k < K_; ++k) a0 += wc[k * n_] * tt[k];
-                const T acc = (a0 + a1) + (a2 + a3);
-                const T vr = vb[r];
-                const T y = m.mode ? bbar[r] + (vr - acc) : bbar[r] + acc;
-                const T z = xg[rlv[r]];
-                const T lnew = lc[r] + rho * (z - y);
-                xn[r] = y;
-                ln[r] = lnew;
-                const double dz = double(z) - double(y);
-                const double dx = double(y) - double(xc[r]);
-                p0 += dz * dz;
-                p1 += dx * dx;
-                p2 += double(z) * double(z);
-                p3 += double(y) * double(y);
-                p4 += double(lnew) * double(lnew);
-            }
-            // each row of 16 lanes sums its values; its first lane leaves
-            // them for wave tw
-            double pq[5] = {p0, p1, p2, p3, p4};
-            row_sum5(pq);
-            if ((lane & 15) == 0) {
-                double* o = red + (wv * 4 + (lane >> 4)) * 8;
-#pragma unroll
-                for (int q = 0; q < 5; ++q) o[q] = pq[q];
-            }
-            // this sweep's emptied exchange words are stored before any
-            // partial sum of this sweep is published
+            __syncthreads();  // B3
+            __syncthreads();  // B4
+            // its loads of the t phase have long returned: waiting for them
+            // here, before any store of this phase, keeps the later waits on
+            // them (group sums, totals) from also waiting for those stores
             __builtin_amdgcn_s_waitcnt(0);
-        }
-        __syncthreads();
-        stamp(3);
-        // wave tw's loads of the t phase have long returned (the other waves
-        // have nothing outstanding): waiting for them here, on every wave's
-        // path and before any store of this phase, keeps the later waits on
-        // them (group sums, totals) from also waiting for those stores
-        __builtin_amdgcn_s_waitcnt(0);
-        // partial sums for the next global update; publish boundary slots
-        for (int v = tid; tid < g_threads && v < V; v += g_threads) {
-            T acc = T(0);
-            for (int q = coff[v]; q < coff[v + 1]; ++q) {
-                const int r = crow[q];
-                acc += xn[r] - ln[r] * irho;
-            }
-            ownp[v] = acc;
-            publish(bnx, v, acc);
-        }
-        if (wv == tw) {
             // group-sum words of sweep done - 1 that were still empty when
             // loaded in the t phase are loaded again, before this phase's
             // stores (the wait above made their values known)
@@ -623,11 +509,140 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             sq_ = group_sum(sq_, 8);
             if (leader && done >= 1) group_sums(done);
             if (lane < 40 && (lane & 7) == 0) st_agent(ring1(done + 1) + (lane >> 3) * P + blockIdx.x, sq_);
+            ++done;
         }
-        stamp(4);
-        ++done;
-        cur = nx;
-        stamp(5);
+    } else {
+        int cur = 0;  // x_s, lambda buffer of sweep `done` (sweep k lives in buffer k % 3, its x in k % 4)
+        while (done < a.max_iter) {
+            const int nx = cur == 2 ? 0 : cur + 1;
+            const int bp = int(done & 1);  // exchange-word parity
+            T* bcur = a.bpart + int64_t(bp) * ns;
+            T* bnx = a.bpart + int64_t(bp ^ 1) * ns;
+            T* xg = XL(int((done + 1) & 3));
+            // closed_1: clipped average of the copies
+            for (int v = tid; v < V; v += g_threads) {
+                const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
+                T xv = (s - crho[v]) * vcnt[v];
+                xv = xv < vlo[v] ? vlo[v] : xv;
+                xv = xv > vhi[v] ? vhi[v] : xv;
+                xg[v] = xv;
+            }
+            if (PROF && tid == 0) tprof[7] += wall_clock64() - tlast;  // the workgroup's own global update, inside phase 0
+            __syncthreads();  // B1
+            if (ok_lds == 0) {
+                ok = false;
+                break;
+            }
+            if (done >= 3 && decide()) {
+                // x_s, lambda of sweep done - 2 are intact (this sweep's
+                // local update has not run), and so is its x (buffer % 4)
+                result = done - 2;
+                stopped = true;
+                break;
+            }
+            stamp(0);
+            // v = B_s x + lambda_s / rho
+            const T* lc = LAM(cur);
+            for (int r = tid; r < R; r += g_threads) vb[r] = xg[rlv[r]] + lc[r] * irho;
+            __syncthreads();  // B2
+            stamp(1);
+            // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
+            for (int base = 0; base < TK * GA; base += g_threads) {
+                const int q0 = base + tid;
+                const int task = q0 / GA, sub = q0 - task * GA;
+                T acc = T(0);
+                if (task < TK) {
+                    const SubLds m = meta[tks[task]];
+                    const T* wr = W + m.w0 + (task - m.t0) * m.n;
+                    const T* vv = vb + m.row0;
+                    // four products per step, their eight loads issued together
+                    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+                    int j = sub;
+                    for (; j + 3 * GA < m.n; j += 4 * GA) {
+                        const T w0 = wr[j], w1 = wr[j + GA], w2 = wr[j + 2 * GA], w3 = wr[j + 3 * GA];
+                        const T v0 = vv[j], v1 = vv[j + GA], v2 = vv[j + 2 * GA], v3 = vv[j + 3 * GA];
+                        a0 += w0 * v0;
+                        a1 += w1 * v1;
+                        a2 += w2 * v2;
+                        a3 += w3 * v3;
+                    }
+                    for (; j < m.n; j += GA) a0 += wr[j] * vv[j];
+                    acc = (a0 + a1) + (a2 + a3);
+                }
+                acc = group_sum(acc, GA);
+                if (task < TK && sub == 0) tb[task] = acc;
+            }
+            __syncthreads();  // B3
+            stamp(2);
+            // closed_2 in rank form, then ADMM-3; residual sums in FP64
+            const T* xc = XS(cur);
+            T* xn = XS(nx);
+            T* ln = LAM(nx);
+            {
+                double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
+                for (int r = tid; r < R; r += g_threads) {
+                    const SubLds m = meta[rsub[r]];
+                    const int j = r - m.row0;
+                    const T* wc = W + m.w0 + j;
+                    const T* tt = tb + m.t0;
+                    // four products per step, their eight loads issued together
+                    const int n_ = m.n, K_ = m.k;
+                    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+                    int k = 0;
+                    for (; k + 4 <= K_; k += 4) {
+                        const T w0 = wc[k * n_], w1 = wc[(k + 1) * n_], w2 = wc[(k + 2) * n_], w3 = wc[(k + 3) * n_];
+                        const T t0 = tt[k], t1 = tt[k + 1], t2 = tt[k + 2], t3 = tt[k + 3];
+                        a0 += w0 * t0;
+                        a1 += w1 * t1;
+                        a2 += w2 * t2;
+                        a3 += w3 * t3;
+                    }
+                    for (; k < K_; ++k) a0 += wc[k * n_] * tt[k];
+                    const T acc = (a0 + a1) + (a2 + a3);
+                    const T vr = vb[r];
+                    const T y = m.mode ? bbar[r] + (vr - acc) : bbar[r] + acc;
+                    const T z = xg[rlv[r]];
+                    const T lnew = lc[r] + rho * (z - y);
+                    xn[r] = y;
+                    ln[r] = lnew;
+                    const double dz = double(z) - double(y);
+                    const double dx = double(y) - double(xc[r]);
+                    p0 += dz * dz;
+                    p1 += dx * dx;
+                    p2 += double(z) * double(z);
+                    p3 += double(y) * double(y);
+                    p4 += double(lnew) * double(lnew);
+                }
+                // each row of 16 lanes sums its values; its first lane leaves
+                // them for wave tw
+                double pq[5] = {p0, p1, p2, p3, p4};
+                row_sum5(pq);
+                if ((lane & 15) == 0) {
+                    double* o = red + (wv * 4 + (lane >> 4)) * 8;
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) o[q] = pq[q];
+                }
+                // this sweep's emptied exchange words are stored before any
+                // partial sum of this sweep is published
+                __builtin_amdgcn_s_waitcnt(0);
+            }
+            __syncthreads();  // B4
+            stamp(3);
+            // partial sums for the next global update; publish boundary slots
+            for (int v = tid; v < V; v += g_threads) {
+                T acc = T(0);
+                for (int q = coff[v]; q < coff[v + 1]; ++q) {
+                    const int r = crow[q];
+                    acc += xn[r] - ln[r] * irho;
+                }
+                ownp[v] = acc;
+                publish(bnx, v, acc);
+            }
+            stamp(4);
+            ++done;
+            cur = nx;
+            stamp(5);
+        }
     }
     if (ok && !stopped) {
         // max_iter reached: the group sums of the last sweep, then the

@@ -200,7 +200,7 @@ Plan make_plan(const ConsensusLP& lp, const std::vector<int32_t>& rank, bool fp3
         // one row per lane of the work waves, plus the wave that runs the
         // termination test
         if (bt <= 0) bt = int32_t(std::min<int64_t>(1024, std::max<int64_t>(1, (max_rows + 63) / 64) * 64 + 64));
-        if (bt < 64 || bt > 1024 || bt % 64 != 0) fail(LDOPF_INVALID_ARGUMENT, "block_threads must be a multiple of 64 in [64, 1024]");
+        if (bt < 128 || bt > 1024 || bt % 64 != 0) fail(LDOPF_INVALID_ARGUMENT, "block_threads must be a multiple of 64 in [128, 1024]");
         pl.block_threads = bt;
         // recompute the LDS need with the real wave count
         int64_t lds = 0;
