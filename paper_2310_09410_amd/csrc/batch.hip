@@ -268,8 +268,12 @@ __global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
 //   per-scenario class: t = W v (wave w takes basis rows w, w + 4, ...), then
 //     y = bbar + v - W't (mode 1) or bbar + W't (mode 0) per row.
 // Then lambda += rho (z - y), and the FP64 residual sums per scenario.
+// Four blocks per CU (four waves per SIMD, at most 128 VGPRs) for the common
+// subsystem width: the phases of a subsystem (row loads, MFMA or operator
+// streams, barriers) then overlap across blocks. The wider variants keep
+// their registers instead (a cap would make them spill).
 template <int RPW>
-__global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
+__global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(BatchArgs a) {
     if (a.ctrl[1]) return;
     extern __shared__ __align__(16) float sm[];
     float* Vs = sm;                         // [nmax][kZS]
@@ -387,66 +391,39 @@ __global__ __launch_bounds__(256) void batch_local_kernel(BatchArgs a) {
                 }
             } else {
                 const int K = m.K, mode = m.mode;
-                const float* Wb = a.W + m.off * Bp + sc;
+                const float* Wb = a.W + m.off * Bp;
                 const int nB = n * Bp;
-                // T = W V: the wave's basis rows k = wv, wv + 4, ... together,
-                // eight columns per step, so that all their loads are in
-                // flight at once (the bounds are uniform over the wave)
-                constexpr int KPW = 5;
-                for (int k0 = wv; k0 < K; k0 += 4 * KPW) {
-                    float t[KPW][2];
+                for (int k = wv; k < K; k += 4) {
+                    const int o0 = k * nB + sc;
+                    float t[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    int j = 0;
+                    for (; j + 8 <= n; j += 8) {
+                        float w[8];
 #pragma unroll
-                    for (int i = 0; i < KPW; ++i) t[i][0] = t[i][1] = 0.f;
-                    for (int j0 = 0; j0 < n; j0 += 8) {
-                        float v[8], w[KPW][8];
+                        for (int u = 0; u < 8; ++u) w[u] = Wb[o0 + (j + u) * Bp];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) v[u] = j0 + u < n ? Vs[(j0 + u) * kZS + lane] : 0.f;
-#pragma unroll
-                        for (int i = 0; i < KPW; ++i) {
-                            const int k = k0 + 4 * i;
-#pragma unroll
-                            for (int u = 0; u < 8; ++u)
-                                w[i][u] = (k < K && j0 + u < n) ? Wb[k * nB + (j0 + u) * Bp] : 0.f;
-                        }
-#pragma unroll
-                        for (int i = 0; i < KPW; ++i)
-#pragma unroll
-                            for (int u = 0; u < 8; ++u) t[i][u & 1] += w[i][u] * v[u];
+                        for (int u = 0; u < 8; ++u) t[u] += w[u] * Vs[(j + u) * kZS + lane];
                     }
-#pragma unroll
-                    for (int i = 0; i < KPW; ++i)
-                        if (k0 + 4 * i < K) Ts[(k0 + 4 * i) * kZS + lane] = t[i][0] + t[i][1];
+                    for (; j < n; ++j) t[0] += Wb[o0 + j * Bp] * Vs[j * kZS + lane];
+                    Ts[k * kZS + lane] = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
                 }
                 __syncthreads();
-                // U = W' T on the wave's rows j = wv, wv + 4, ... together, a
-                // few basis rows per step
-                constexpr int KB = RPW <= 10 ? 4 : (RPW <= 16 ? 2 : 1);
-                float uacc[RPW];
+                for (int j = wv; j < n; j += 4) {
+                    const int o0 = j * Bp + sc;
+                    float u[4] = {0.f, 0.f, 0.f, 0.f};
+                    int k = 0;
+                    for (; k + 4 <= K; k += 4) {
+                        float w[4];
 #pragma unroll
-                for (int r = 0; r < RPW; ++r) uacc[r] = 0.f;
-                for (int k0 = 0; k0 < K; k0 += KB) {
-                    float tk[KB], w[RPW][KB];
+                        for (int e = 0; e < 4; ++e) w[e] = Wb[o0 + (k + e) * nB];
 #pragma unroll
-                    for (int e = 0; e < KB; ++e) tk[e] = k0 + e < K ? Ts[(k0 + e) * kZS + lane] : 0.f;
-#pragma unroll
-                    for (int r = 0; r < RPW; ++r) {
-                        const int j = wv + 4 * r;
-#pragma unroll
-                        for (int e = 0; e < KB; ++e) w[r][e] = (j < n && k0 + e < K) ? Wb[(k0 + e) * nB + j * Bp] : 0.f;
+                        for (int e = 0; e < 4; ++e) u[e] += w[e] * Ts[(k + e) * kZS + lane];
                     }
-#pragma unroll
-                    for (int r = 0; r < RPW; ++r)
-#pragma unroll
-                        for (int e = 0; e < KB; ++e) uacc[r] += w[r][e] * tk[e];
-                }
-#pragma unroll
-                for (int r = 0; r < RPW; ++r) {
-                    const int j = wv + 4 * r;
-                    if (j < n) {
-                        const float vj = Vs[j * kZS + lane];
-                        const float bj = Ys[j * kZS + lane];
-                        Ys[j * kZS + lane] = mode ? bj + (vj - uacc[r]) : bj + uacc[r];
-                    }
+                    for (; k < K; ++k) u[0] += Wb[o0 + k * nB] * Ts[k * kZS + lane];
+                    const float acc = (u[0] + u[1]) + (u[2] + u[3]);
+                    const float vj = Vs[j * kZS + lane];
+                    const float bj = Ys[j * kZS + lane];
+                    Ys[j * kZS + lane] = mode ? bj + (vj - acc) : bj + acc;
                 }
             }
             __syncthreads();
