@@ -114,3 +114,26 @@ def test_default_options():
     o = P.ldopf_default_options()
     assert o.rho == 100.0 and o.eps_rel == 1e-4 and o.max_iter == 1000000
     assert o.precision == 0 and o.residual_form == 0 and o.check_termination == 1
+
+
+@pytest.mark.parametrize("field,value", [
+    ("block_threads", 64),     # one wave: no room for the test wave beside a row wave
+    ("block_threads", 96),     # not a multiple of 64
+    ("block_threads", 1088),   # above 1024
+    ("rows_per_part", -1),
+    ("rho", 0.0),
+    ("eps_rel", -1.0),
+    ("max_iter", -1),
+    ("check_termination", 2),
+])
+def test_options_out_of_range_are_rejected_before_any_device_work(field, value):
+    """Option bounds (include/ldopf.h, ldopf_options) are checked on the host
+    before the device is touched, so they fail the same way with or without
+    a GPU."""
+    import paper_2310_09410_amd as P
+    from paper_2310_09410_amd.ldopf import LdopfError
+    o = P.ldopf_default_options()
+    setattr(o, field, value)
+    with pytest.raises(LdopfError) as e:
+        P.ldopf_create(dict(feeder("13")), o)
+    assert e.value.code == -1
