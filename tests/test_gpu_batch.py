@@ -111,3 +111,27 @@ def test_batch_tuner_keeps_results(gpu, tmp_path):
     b.solve()
     for k in range(4):
         np.testing.assert_array_equal(a.get_global(k), b.get_global(k))
+
+
+def test_batch_full_size_sampled_scenarios(gpu):
+    """The batched workload bench.py times (2500-bus feeder x 256 scenarios,
+    the bench's scenario factors, tiling chosen by the tuner) for 100 fixed
+    sweeps; three sampled scenarios against oracle solves of their scaled
+    networks."""
+    P = gpu
+    net = feeder("2500")
+    from synth import scenario_factors
+    f = scenario_factors(net, 256)
+    T = 100
+    b = P.ldopf_batch_create(net, f)
+    b.tune(None)
+    b.set_options(P.ldopf_default_options(precision=1, max_iter=T, check_termination=0))
+    b.reset()
+    st = b.solve()
+    assert st.sweeps == T
+    for k in (0, 131, 255):
+        ref = _oracle(net, f[k], max_iter=T, check=False)
+        xs, lam = b.get_local(k)
+        assert b.scenario(k).iterations == T
+        assert rel_err(b.get_global(k), ref.x) <= 1e-4
+        assert rel_err(xs, ref.xs) <= 1e-4

@@ -165,3 +165,53 @@ def test_partition_independence(gpu):
     a.solve()
     b.solve()
     assert rel_err(a.get_global(), b.get_global()) <= 1e-10
+
+
+# ------------------------------------------------- the benchmarked workload
+# The 8500-bus feeder with the default options is the workload bench.py
+# times, in the same automatic plan (one workgroup per CU, row waves plus
+# the test wave); the oracle runs it in a few seconds, so every element is
+# compared, not a sample.
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-6), (1, 1e-4)])
+def test_full_size_8500_fixed_sweeps(gpu, precision, tol):
+    P = gpu
+    T = 300
+    prob = P.ldopf_create(feeder("8500"), _opts(P, max_iter=T, check_termination=0, precision=precision))
+    st = prob.solve()
+    assert st.iterations == T
+    ref = _oracle_fixed("8500", T)
+    xs, lam = prob.get_local()
+    assert rel_err(prob.get_global(), ref.x) <= tol
+    assert rel_err(xs, ref.xs) <= tol
+    if precision == 0:
+        assert rel_err(lam, ref.lam) <= tol
+        np.testing.assert_allclose(prob.get_history(), ref.history, rtol=1e-6, atol=1e-12)
+
+
+def test_full_size_8500_converged(gpu):
+    """To eps_rel = 1e-4 at full size (252k sweeps, too many for the oracle):
+    the returned x, x_s and lambda are the state of the sweep that passed the
+    test (its primal residual and both tolerances, recomputed on the host from
+    them, are the recorded ones, and the recorded test holds), and the
+    objective is within 1e-3 of the LP optimum (HiGHS), the gap the oracle
+    itself shows at this tolerance on the 123-bus feeder."""
+    from oracle import central
+    P = gpu
+    prob = P.ldopf_create(feeder("8500"))
+    st = prob.solve()
+    assert st.converged == 1
+    k = st.iterations
+    H = prob.get_history()
+    assert H.shape[0] >= k
+    pres_k, dres_k, eps_p_k, eps_d_k = H[k - 1]
+    assert pres_k <= eps_p_k and dres_k <= eps_d_k
+    gidx = np.concatenate([s.gidx for s in oracle_lp("8500").subs])
+    x = prob.get_global()
+    xs, lam = prob.get_local()
+    z = x[gidx]
+    assert np.linalg.norm(z - xs) == pytest.approx(pres_k, rel=1e-9)
+    assert 1e-4 * max(np.linalg.norm(z), np.linalg.norm(xs)) == pytest.approx(eps_p_k, rel=1e-12)
+    assert 1e-4 * np.linalg.norm(lam) == pytest.approx(eps_d_k, rel=1e-12)
+    f_lp, _, _ = central.solve_central(feeder("8500"))
+    assert abs(prob.objective() - f_lp) / max(1.0, abs(f_lp)) <= 1e-3
