@@ -47,7 +47,14 @@ def algorithmic_bytes_per_sweep(sizes, w: int) -> float:
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    """Hash of the sweep kernel's source with comments and whitespace removed,
+    so that the stored counters stay valid across comment-only edits and
+    lapse with any change of code."""
+    src = open(KERNEL_SRC, encoding="utf-8").read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = re.sub(r"\s+", "", src)
+    return hashlib.sha256(src.encode()).hexdigest()
 
 
 def stored_traffic():

@@ -17,10 +17,11 @@
 //    workgroup touches, local update closed_2 in rank form, dual update
 //    ADMM-3, residual partial sums in FP64, publication of the boundary
 //    partial sums to the neighbouring workgroups, and the termination test
-//    of Section III-C evaluated identically by every workgroup. There is no
-//    grid barrier: a workgroup waits only for the exchange words it reads
-//    (boundary partial sums of its neighbours, every part's residual sums
-//    of the previous sweep).
+//    of Section III-C evaluated identically by every workgroup, three
+//    sweeps later, by a wave of its own. There is no grid barrier: a
+//    workgroup waits only for the exchange words it reads (boundary partial
+//    sums of its neighbours; the residual sums, summed in two levels through
+//    group leaders, of a sweep finished two sweeps earlier).
 //
 // The local update in rank form: with W the K_s rows of the smaller of the
 // row-space basis (mode 1) and the complement basis (mode 0),
