@@ -197,6 +197,14 @@ __device__ inline int task_lanes(int tasks, int threads) {
 
 }  // namespace
 
+// A workgroup-uniform 32-bit value kept in a vector register: LDS addresses
+// are formed in vector registers in any case, while the scalar register file
+// is the one this kernel runs short of.
+__device__ inline uint32_t in_vgpr(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 template <typename T, bool PROF>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -206,31 +214,34 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     const PartInfo pi = a.parts[blockIdx.x];
     const LdsLayout L = lds_layout(sizeof(T), uint32_t(pi.w_words), uint32_t(pi.n_row), uint32_t(pi.n_tk),
                                    uint32_t(pi.n_var), uint32_t(pi.n_sub), uint32_t(nw));
-    T* W = reinterpret_cast<T*>(smem + L.W);
-    T* bbar = reinterpret_cast<T*>(smem + L.bbar);
+    T* W = reinterpret_cast<T*>(smem + in_vgpr(L.W));
+    T* bbar = reinterpret_cast<T*>(smem + in_vgpr(L.bbar));
     // state buffers, selected by offset from the shared base so that every
     // access stays an LDS access (a table of pointers would not)
-    const uint32_t s_xs = L.xs[1] - L.xs[0], s_lam = L.lam[1] - L.lam[0], s_xl = L.xloc[1] - L.xloc[0];
-    auto XS = [&](int b) { return reinterpret_cast<T*>(smem + L.xs[0] + uint32_t(b) * s_xs); };
-    auto LAM = [&](int b) { return reinterpret_cast<T*>(smem + L.lam[0] + uint32_t(b) * s_lam); };
-    auto XL = [&](int b) { return reinterpret_cast<T*>(smem + L.xloc[0] + uint32_t(b) * s_xl); };
-    T* vb = reinterpret_cast<T*>(smem + L.v);
-    T* tb = reinterpret_cast<T*>(smem + L.t);
-    T* ownp = reinterpret_cast<T*>(smem + L.ownp);
-    T* crho = reinterpret_cast<T*>(smem + L.crho);
-    T* vlo = reinterpret_cast<T*>(smem + L.lo);
-    T* vhi = reinterpret_cast<T*>(smem + L.hi);
-    T* vcnt = reinterpret_cast<T*>(smem + L.cnt);
-    int32_t* sbase = reinterpret_cast<int32_t*>(smem + L.slot_lo);
-    int32_t* sm_ = reinterpret_cast<int32_t*>(smem + L.slot_hi);
-    int32_t* sme = reinterpret_cast<int32_t*>(smem + L.slot_own);
-    uint16_t* rlv = reinterpret_cast<uint16_t*>(smem + L.row_lvar);
-    uint16_t* rsub = reinterpret_cast<uint16_t*>(smem + L.row_sub);
-    uint16_t* coff = reinterpret_cast<uint16_t*>(smem + L.copy_off);
-    uint16_t* crow = reinterpret_cast<uint16_t*>(smem + L.copy_rows);
-    uint16_t* tks = reinterpret_cast<uint16_t*>(smem + L.tk_sub);
-    SubLds* meta = reinterpret_cast<SubLds*>(smem + L.meta);
-    double* red = reinterpret_cast<double*>(smem + L.red);
+    const uint32_t s_xs = in_vgpr(L.xs[1] - L.xs[0]), s_lam = in_vgpr(L.lam[1] - L.lam[0]), s_xl = in_vgpr(L.xloc[1] - L.xloc[0]);
+    const uint32_t o_xs = in_vgpr(L.xs[0]), o_lam = in_vgpr(L.lam[0]), o_xl = in_vgpr(L.xloc[0]);
+    auto XS = [&](int b) { return reinterpret_cast<T*>(smem + o_xs + uint32_t(b) * s_xs); };
+    auto LAM = [&](int b) { return reinterpret_cast<T*>(smem + o_lam + uint32_t(b) * s_lam); };
+    auto XL = [&](int b) { return reinterpret_cast<T*>(smem + o_xl + uint32_t(b) * s_xl); };
+    T* vb = reinterpret_cast<T*>(smem + in_vgpr(L.v));
+    T* tb = reinterpret_cast<T*>(smem + in_vgpr(L.t));
+    T* ownp = reinterpret_cast<T*>(smem + in_vgpr(L.ownp));
+    T* crho = reinterpret_cast<T*>(smem + in_vgpr(L.crho));
+    T* vlo = reinterpret_cast<T*>(smem + in_vgpr(L.lo));
+    T* vhi = reinterpret_cast<T*>(smem + in_vgpr(L.hi));
+    T* vcnt = reinterpret_cast<T*>(smem + in_vgpr(L.cnt));
+    int32_t* sbase = reinterpret_cast<int32_t*>(smem + in_vgpr(L.slot_lo));
+    int32_t* sm_ = reinterpret_cast<int32_t*>(smem + in_vgpr(L.slot_hi));
+    int32_t* sme = reinterpret_cast<int32_t*>(smem + in_vgpr(L.slot_own));
+    uint16_t* rlv = reinterpret_cast<uint16_t*>(smem + in_vgpr(L.row_lvar));
+    uint16_t* rsub = reinterpret_cast<uint16_t*>(smem + in_vgpr(L.row_sub));
+    uint16_t* coff = reinterpret_cast<uint16_t*>(smem + in_vgpr(L.copy_off));
+    uint16_t* crow = reinterpret_cast<uint16_t*>(smem + in_vgpr(L.copy_rows));
+    uint16_t* tks = reinterpret_cast<uint16_t*>(smem + in_vgpr(L.tk_sub));
+    SubLds* meta = reinterpret_cast<SubLds*>(smem + in_vgpr(L.meta));
+    uint2* tkm = reinterpret_cast<uint2*>(smem + in_vgpr(L.tk_m));
+    uint2* rwm = reinterpret_cast<uint2*>(smem + in_vgpr(L.row_m));
+    double* red = reinterpret_cast<double*>(smem + in_vgpr(L.red));
     double* tot = red + 32 * nw;  // after the row sums [waves][4][8]
 
     const T rho = T(a.rho);
@@ -267,6 +278,19 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         sme[v] = a.var_slot[pi.var_begin + v];
     }
     for (int q = tid; q < TK; q += nt) tks[q] = a.tk_sub[pi.tk_begin + q];
+    __syncthreads();
+    // each task's and each row's operator offsets in one word, so that the
+    // phases reach their operands with one LDS read instead of two
+    // (operator words, rows and tasks of a part all stay below 2^16)
+    for (int q = tid; q < TK; q += nt) {
+        const SubLds m = meta[tks[q]];
+        tkm[q] = make_uint2((m.w0 + uint32_t(q - m.t0) * m.n) | (uint32_t(m.row0) << 16), m.n);
+    }
+    for (int r = tid; r < R; r += nt) {
+        const SubLds m = meta[rsub[r]];
+        rwm[r] = make_uint2((m.w0 + uint32_t(r - m.row0)) | (uint32_t(m.t0) << 16),
+                            uint32_t(m.n) | ((uint32_t(m.k) | (uint32_t(m.mode) << 7)) << 8));
+    }
     for (int i = wv; i < pi.n_sub; i += nw) {
         const SubMeta m = a.subs[pi.sub_begin + i];
         const int kn = int(m.k) * int(m.n);
@@ -553,13 +577,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                 const int task = q0 / GA, sub = q0 - task * GA;
                 T acc = T(0);
                 if (task < TK) {
-                    const SubLds m = meta[tks[task]];
-                    const T* wr = W + m.w0 + (task - m.t0) * m.n;
-                    const T* vv = vb + m.row0;
+                    const uint2 tm = tkm[task];
+                    const T* wr = W + (tm.x & 0xffffu);
+                    const T* vv = vb + (tm.x >> 16);
+                    const int n_t = int(tm.y);
                     // four products per step, their eight loads issued together
                     T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
                     int j = sub;
-                    for (; j + 3 * GA < m.n; j += 4 * GA) {
+                    for (; j + 3 * GA < n_t; j += 4 * GA) {
                         const T w0 = wr[j], w1 = wr[j + GA], w2 = wr[j + 2 * GA], w3 = wr[j + 3 * GA];
                         const T v0 = vv[j], v1 = vv[j + GA], v2 = vv[j + 2 * GA], v3 = vv[j + 3 * GA];
                         a0 += w0 * v0;
@@ -567,7 +592,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                         a2 += w2 * v2;
                         a3 += w3 * v3;
                     }
-                    for (; j < m.n; j += GA) a0 += wr[j] * vv[j];
+                    for (; j < n_t; j += GA) a0 += wr[j] * vv[j];
                     acc = (a0 + a1) + (a2 + a3);
                 }
                 acc = group_sum(acc, GA);
@@ -582,12 +607,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             {
                 double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
                 for (int r = tid; r < R; r += g_threads) {
-                    const SubLds m = meta[rsub[r]];
-                    const int j = r - m.row0;
-                    const T* wc = W + m.w0 + j;
-                    const T* tt = tb + m.t0;
+                    const uint2 rm = rwm[r];
+                    const T* wc = W + (rm.x & 0xffffu);
+                    const T* tt = tb + (rm.x >> 16);
                     // four products per step, their eight loads issued together
-                    const int n_ = m.n, K_ = m.k;
+                    const int n_ = int(rm.y & 0xffu), K_ = int((rm.y >> 8) & 0x7fu);
+                    const bool mode1 = ((rm.y >> 15) & 1u) != 0;
                     T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
                     int k = 0;
                     for (; k + 4 <= K_; k += 4) {
@@ -601,7 +626,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                     for (; k < K_; ++k) a0 += wc[k * n_] * tt[k];
                     const T acc = (a0 + a1) + (a2 + a3);
                     const T vr = vb[r];
-                    const T y = m.mode ? bbar[r] + (vr - acc) : bbar[r] + acc;
+                    const T y = mode1 ? bbar[r] + (vr - acc) : bbar[r] + acc;
                     const T z = xg[rlv[r]];
                     const T lnew = lc[r] + rho * (z - y);
                     xn[r] = y;

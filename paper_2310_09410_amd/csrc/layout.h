@@ -17,6 +17,7 @@ struct LdsLayout {
     uint32_t W, bbar, xs[3], lam[3], v, t, xloc[4], ownp, crho, lo, hi, cnt;  // T arrays
     uint32_t slot_lo, slot_hi, slot_own;                                         // int32 per var
     uint32_t row_lvar, row_sub, copy_off, copy_rows, tk_sub, meta;                // index arrays
+    uint32_t tk_m, row_m;  // uint2 per task / per row: operator offsets packed at load time
     uint32_t red;                                                                // double [waves][4][8], then [8]
     uint32_t total;
 };
@@ -57,6 +58,8 @@ LDOPF_HD inline LdsLayout lds_layout(uint32_t w, uint32_t w_words, uint32_t rows
     L.copy_rows = take(2 * rows);
     L.tk_sub = take(2 * tks);
     L.meta = take(16 * subs);
+    L.tk_m = take(8 * tks);
+    L.row_m = take(8 * rows);
     L.red = take(8 * 8 * (4 * waves + 1));  // row sums of each wave's 4 rows, then the grid totals
     L.total = o;
     return L;
