@@ -370,6 +370,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     __syncthreads();
 
     const int GA = task_lanes(TK, g_threads);
+    const int lgGA = GA == 8 ? 3 : (GA == 4 ? 2 : (GA == 2 ? 1 : 0));  // GA is a power of two
     // Residual sums, reduced in two levels by wave tw. Level 1: every part's
     // 5 sums of a sweep (ring entry [8][P], quantity-major), read only by its
     // group leader, the first of each kGroup consecutive parts, which adds
@@ -574,7 +575,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
             for (int base = 0; base < TK * GA; base += g_threads) {
                 const int q0 = base + tid;
-                const int task = q0 / GA, sub = q0 - task * GA;
+                const int task = q0 >> lgGA, sub = q0 & (GA - 1);
                 T acc = T(0);
                 if (task < TK) {
                     const uint2 tm = tkm[task];
