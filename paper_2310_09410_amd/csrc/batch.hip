@@ -335,59 +335,48 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
             }
             __syncthreads();
             if (m.cls == 0) {
-                // T = W V: the K rows of W in 16-row tiles against the four
-                // 16-scenario tiles
+                // T = W V: (16-row tile of W, 16-scenario tile) products spread
+                // over the four waves
                 const int K = m.K, mode = m.mode;
-                for (int mt = wv; mt * 16 < K; mt += 4) {
-                    floatx4 acc[4];
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int pq = wv; pq < ((K + 15) >> 4) * 4; pq += 4) {
+                    const int mt = pq >> 2, nt = pq & 3;
+                    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
                     const int ar = mt * 16 + (lane & 15);
                     for (int kk = 0; kk * 4 < n; ++kk) {
                         const int kc = kk * 4 + (lane >> 4);
                         const bool in = kc < n;
                         const float av = (ar < K && in) ? As[ar * n + kc] : 0.f;
-#pragma unroll
-                        for (int nt = 0; nt < 4; ++nt) {
-                            const float bv = in ? Vs[kc * kZS + nt * 16 + (lane & 15)] : 0.f;
-                            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[nt], 0, 0, 0);
-                        }
+                        const float bv = in ? Vs[kc * kZS + nt * 16 + (lane & 15)] : 0.f;
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
                     }
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int row = mt * 16 + 4 * (lane >> 4) + i;
-                            if (row < K) Ts[row * kZS + nt * 16 + (lane & 15)] = acc[nt][i];
-                        }
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = mt * 16 + 4 * (lane >> 4) + i;
+                        if (row < K) Ts[row * kZS + nt * 16 + (lane & 15)] = acc[i];
+                    }
                 }
                 __syncthreads();
-                // U = W' T, then y = bbar + v - U (mode 1) or bbar + U (mode 0)
-                for (int mt = wv; mt * 16 < n; mt += 4) {
-                    floatx4 acc[4];
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+                // U = W' T, then y = bbar + v - U (mode 1) or bbar + U (mode 0),
+                // the tile products spread over the waves the same way
+                for (int pq = wv; pq < ((n + 15) >> 4) * 4; pq += 4) {
+                    const int mt = pq >> 2, nt = pq & 3;
+                    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
                     const int ar = mt * 16 + (lane & 15);
                     for (int kk = 0; kk * 4 < K; ++kk) {
                         const int kc = kk * 4 + (lane >> 4);
                         const bool in = kc < K;
                         const float av = (ar < n && in) ? As[kc * n + ar] : 0.f;
-#pragma unroll
-                        for (int nt = 0; nt < 4; ++nt) {
-                            const float bv = in ? Ts[kc * kZS + nt * 16 + (lane & 15)] : 0.f;
-                            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[nt], 0, 0, 0);
-                        }
+                        const float bv = in ? Ts[kc * kZS + nt * 16 + (lane & 15)] : 0.f;
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
                     }
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int row = mt * 16 + 4 * (lane >> 4) + i;
-                            if (row < n) {
-                                const int e = row * kZS + nt * 16 + (lane & 15);
-                                Ys[e] = mode ? Ys[e] + (Vs[e] - acc[nt][i]) : Ys[e] + acc[nt][i];
-                            }
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = mt * 16 + 4 * (lane >> 4) + i;
+                        if (row < n) {
+                            const int e = row * kZS + nt * 16 + (lane & 15);
+                            Ys[e] = mode ? Ys[e] + (Vs[e] - acc[i]) : Ys[e] + acc[i];
                         }
+                    }
                 }
             } else {
                 const int K = m.K, mode = m.mode;
@@ -426,7 +415,9 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
                     Ys[j * kZS + lane] = mode ? bj + (vj - acc) : bj + acc;
                 }
             }
-            __syncthreads();
+            // the shared class wrote y by tiles: wait for every wave; the
+            // per-scenario class wrote each wave's own rows
+            if (m.cls == 0) __syncthreads();
             // dual update and residual sums on the wave's own rows
             float* XSw = a.XS + row0 * Bp;
             float* LAMw = a.LAM + row0 * Bp;
