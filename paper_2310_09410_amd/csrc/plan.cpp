@@ -143,7 +143,8 @@ Plan make_plan(const ConsensusLP& lp, const std::vector<int32_t>& rank, bool fp3
             pi.n_var = int32_t(nv);
             pi.n_tk = int32_t(t);
             pi.w_words = int32_t(wwords);
-            if (row > 65535 || nv > 65535 || t > 65535) fits = false;
+            // the kernel packs operator offsets, rows and tasks in 16 bits
+            if (row > 65535 || nv > 65535 || t > 65535 || wwords > 65535) fits = false;
             // copies of each part-local var, in row order
             std::vector<uint16_t> cnt(nv + 1, 0);
             for (uint32_t r = 0; r < row; ++r) cnt[pl.row_lvar[pi.row_begin + r] + 1]++;
