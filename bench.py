@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-sweeps", type=int, default=3000, help="oracle sweeps timed for the CPU baseline")
+    ap.add_argument("--cpu-sweeps", type=int, default=6000, help="oracle sweeps timed for the CPU baseline (about 13 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
