@@ -241,6 +241,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     SubLds* meta = reinterpret_cast<SubLds*>(smem + in_vgpr(L.meta));
     uint2* tkm = reinterpret_cast<uint2*>(smem + in_vgpr(L.tk_m));
     uint2* rwm = reinterpret_cast<uint2*>(smem + in_vgpr(L.row_m));
+    uint16_t* vr0 = reinterpret_cast<uint16_t*>(smem + in_vgpr(L.var_r0));
     double* red = reinterpret_cast<double*>(smem + in_vgpr(L.red));
     double* tot = red + 32 * nw;  // after the row sums [waves][4][8]
 
@@ -286,6 +287,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         const SubLds m = meta[tks[q]];
         tkm[q] = make_uint2((m.w0 + uint32_t(q - m.t0) * m.n) | (uint32_t(m.row0) << 16), m.n);
     }
+    for (int v = tid; v < V; v += nt) vr0[v] = crow[coff[v]];
     for (int r = tid; r < R; r += nt) {
         const SubLds m = meta[rsub[r]];
         rwm[r] = make_uint2((m.w0 + uint32_t(r - m.row0)) | (uint32_t(m.t0) << 16),
@@ -656,9 +658,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             __syncthreads();  // B4
             stamp(3);
             // partial sums for the next global update; publish boundary slots
+            // (every variable has a copy in the part; its first copy's row
+            // is read beside the copy range)
             for (int v = tid; v < V; v += g_threads) {
-                T acc = T(0);
-                for (int q = coff[v]; q < coff[v + 1]; ++q) {
+                const int r0 = vr0[v], c0 = coff[v], c1 = coff[v + 1];
+                T acc = T(0) + (xn[r0] - ln[r0] * irho);
+                for (int q = c0 + 1; q < c1; ++q) {
                     const int r = crow[q];
                     acc += xn[r] - ln[r] * irho;
                 }

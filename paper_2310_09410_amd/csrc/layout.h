@@ -18,6 +18,7 @@ struct LdsLayout {
     uint32_t slot_lo, slot_hi, slot_own;                                         // int32 per var
     uint32_t row_lvar, row_sub, copy_off, copy_rows, tk_sub, meta;                // index arrays
     uint32_t tk_m, row_m;  // uint2 per task / per row: operator offsets packed at load time
+    uint32_t var_r0;       // u16 per var: the row of its first copy
     uint32_t red;                                                                // double [waves][4][8], then [8]
     uint32_t total;
 };
@@ -60,6 +61,7 @@ LDOPF_HD inline LdsLayout lds_layout(uint32_t w, uint32_t w_words, uint32_t rows
     L.meta = take(16 * subs);
     L.tk_m = take(8 * tks);
     L.row_m = take(8 * rows);
+    L.var_r0 = take(2 * vars);
     L.red = take(8 * 8 * (4 * waves + 1));  // row sums of each wave's 4 rows, then the grid totals
     L.total = o;
     return L;
