@@ -189,16 +189,18 @@ def test_full_size_8500_fixed_sweeps(gpu, precision, tol):
         np.testing.assert_allclose(prob.get_history(), ref.history, rtol=1e-6, atol=1e-12)
 
 
-def test_full_size_8500_converged(gpu):
-    """To eps_rel = 1e-4 at full size (252k sweeps, too many for the oracle):
-    the returned x, x_s and lambda are the state of the sweep that passed the
-    test (its primal residual and both tolerances, recomputed on the host from
-    them, are the recorded ones, and the recorded test holds), and the
-    objective is within 1e-3 of the LP optimum (HiGHS), the gap the oracle
-    itself shows at this tolerance on the 123-bus feeder."""
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_8500_converged(gpu, precision):
+    """To eps_rel = 1e-4 at full size (252k sweeps, too many for the oracle),
+    in both forms: the returned x, x_s and lambda are the state of the sweep
+    that passed the test (its primal residual and both tolerances, recomputed
+    on the host from them, are the recorded ones, and the recorded test
+    holds; the FP32 state is returned exactly in FP64, and the test sums it
+    in FP64), and the objective is within 1e-3 of the LP optimum (HiGHS),
+    the gap the oracle itself shows at this tolerance on the 123-bus feeder."""
     from oracle import central
     P = gpu
-    prob = P.ldopf_create(feeder("8500"))
+    prob = P.ldopf_create(feeder("8500"), _opts(P, precision=precision))
     st = prob.solve()
     assert st.converged == 1
     k = st.iterations
