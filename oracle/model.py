@@ -351,7 +351,11 @@ def leaves(net: dict) -> np.ndarray:
 def init_values(ix: Index, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
     """Starting value of each global variable's copies (Section V-A): one for a
     squared voltage, the bound midpoint where both bounds are finite, zero
-    (clipped into the box) otherwise."""
+    (clipped into the box) otherwise.
+
+    Pinned by the hand-derived first sweep of the two-bus case
+    (tests/golden/two_bus.json, "first_sweep"), whose first global iterate
+    is clip(x_init - c / (rho N))."""
     out = np.clip(np.zeros(ix.n), lo, hi)
     both = np.isfinite(lo) & np.isfinite(hi)
     out[both] = 0.5 * (lo[both] + hi[both])

@@ -19,9 +19,15 @@ SOURCES = ["assemble.cpp", "plan.cpp", "api.cpp", "serve.cpp", "device.hip", "ba
 
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 arithmetic.
 HIP_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
+    "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
+]
+# Host-only sources (assembly, planning, the C ABI, the serving runtime) hold
+# no device code: plain C++ against the HIP runtime headers.
+CXX_FLAGS = [
+    "-x", "c++", "-D__HIP_PLATFORM_AMD__=1", "-isystem", "/opt/rocm/include",
+    "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wno-unused-result",
 ]
 
 
@@ -39,8 +45,8 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [hipcc(), *lang, *HIP_FLAGS, "-c", path, "-o", obj]
+        flags = HIP_FLAGS if src.endswith(".hip") else CXX_FLAGS
+        cmd = [hipcc(), *flags, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -93,41 +93,61 @@ struct ldopf_server {
 namespace {
 
 void finish_request(ldopf_server& srv, Request& r) {
-    // copy results to the host, release device memory and the slot
-    ldopf_problem& p = *r.prob;
+    // Everything slow happens first, outside the lock and into locals: wait
+    // for the solve, copy the results to the host, free the device memory.
+    // The request stays RUNNING meanwhile, so no client can release it.
+    ldopf_problem* p = r.prob;
+    ldopf_status status{};
+    int32_t code = LDOPF_OK;
+    std::string detail;
+    std::vector<double> x, xs, lam;
     try {
-        r.code = problem_finish(p, &r.status);
-        const int64_t n = p.lp.n, nl = int64_t(p.lp.gidx.size());
-        r.x.resize(n);
-        r.xs.resize(nl);
-        r.lam.resize(nl);
-        hip_check(hipMemcpyAsync(r.x.data(), p.x.p, n * 8, hipMemcpyDeviceToHost, p.stream), "download x");
-        hip_check(hipMemcpyAsync(r.xs.data(), p.xs.p, nl * 8, hipMemcpyDeviceToHost, p.stream), "download x_s");
-        hip_check(hipMemcpyAsync(r.lam.data(), p.lam.p, nl * 8, hipMemcpyDeviceToHost, p.stream), "download lambda");
-        hip_check(hipStreamSynchronize(p.stream), "download results");
-        r.state = (r.code == LDOPF_OK || r.code == LDOPF_NOT_CONVERGED) ? LDOPF_REQ_DONE : LDOPF_REQ_FAILED;
+        code = problem_finish(*p, &status);
+        const int64_t n = p->lp.n, nl = int64_t(p->lp.gidx.size());
+        x.resize(n);
+        xs.resize(nl);
+        lam.resize(nl);
+        hip_check(hipMemcpyAsync(x.data(), p->x.p, n * 8, hipMemcpyDeviceToHost, p->stream), "download x");
+        hip_check(hipMemcpyAsync(xs.data(), p->xs.p, nl * 8, hipMemcpyDeviceToHost, p->stream), "download x_s");
+        hip_check(hipMemcpyAsync(lam.data(), p->lam.p, nl * 8, hipMemcpyDeviceToHost, p->stream), "download lambda");
+        hip_check(hipStreamSynchronize(p->stream), "download results");
     } catch (const Error& e) {
-        r.code = e.code;
-        r.detail = e.detail;
-        r.state = LDOPF_REQ_FAILED;
+        code = e.code;
+        detail = e.detail;
     }
-    delete r.prob;
-    r.prob = nullptr;
-    r.t_done = Clock::now();
-    std::lock_guard<std::mutex> lk(srv.mu);
-    srv.slot_req[r.slot] = -1;
-    srv.bytes_in_use -= r.bytes;
-    srv.units_in_use -= r.units;
-    srv.running--;
-    if (r.state == LDOPF_REQ_DONE) {
-        srv.completed++;
-        srv.latencies_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
-        srv.t_last = r.t_done;
-    } else {
-        srv.failed++;
+    delete p;
+    const bool ok = code == LDOPF_OK || code == LDOPF_NOT_CONVERGED;
+    const Clock::time_point t_done = Clock::now();
+    ConsensusLP lp_drop;  // the host LP is freed after the lock is released
+    {
+        // One critical section publishes the request: results, status and
+        // the server's bookkeeping, and the state last. A client can see
+        // DONE (and release the request) only after this section, and the
+        // scheduler touches the request no more after it.
+        std::lock_guard<std::mutex> lk(srv.mu);
+        r.prob = nullptr;
+        r.status = status;
+        r.code = code;
+        r.detail = std::move(detail);
+        r.x = std::move(x);
+        r.xs = std::move(xs);
+        r.lam = std::move(lam);
+        r.t_done = t_done;
+        lp_drop = std::move(r.lp);
+        srv.slot_req[r.slot] = -1;
+        srv.bytes_in_use -= r.bytes;
+        srv.units_in_use -= r.units;
+        srv.running--;
+        if (ok) {
+            srv.completed++;
+            srv.latencies_ms.push_back(std::chrono::duration<double, std::milli>(t_done - r.t_submit).count());
+            srv.t_last = t_done;
+        } else {
+            srv.failed++;
+        }
+        r.state = ok ? LDOPF_REQ_DONE : LDOPF_REQ_FAILED;
+        srv.cv_done.notify_all();
     }
-    r.lp = ConsensusLP();  // host LP no longer needed
-    srv.cv_done.notify_all();
 }
 
 }  // namespace
@@ -306,11 +326,19 @@ int ldopf_server_wait(ldopf_server* srv, int64_t req_id, double timeout_s, int32
     return guard([&] {
         need(srv, "server");
         std::unique_lock<std::mutex> lk(srv->mu);
-        auto it = srv->reqs.find(req_id);
-        if (it == srv->reqs.end()) fail(LDOPF_INVALID_ARGUMENT, "unknown request id");
-        Request& r = *it->second;
+        if (srv->reqs.find(req_id) == srv->reqs.end()) fail(LDOPF_INVALID_ARGUMENT, "unknown request id");
         const auto until = Clock::now() + std::chrono::duration<double>(timeout_s < 0 ? 1e9 : timeout_s);
-        srv->cv_done.wait_until(lk, until, [&] { return r.state == LDOPF_REQ_DONE || r.state == LDOPF_REQ_FAILED; });
+        // the request is looked up again after every wake-up: another thread
+        // may have released it meanwhile
+        auto finished = [&] {
+            auto it = srv->reqs.find(req_id);
+            return it == srv->reqs.end() || it->second->state == LDOPF_REQ_DONE ||
+                   it->second->state == LDOPF_REQ_FAILED;
+        };
+        srv->cv_done.wait_until(lk, until, finished);
+        auto it = srv->reqs.find(req_id);
+        if (it == srv->reqs.end()) fail(LDOPF_INVALID_ARGUMENT, "request released while waiting");
+        const Request& r = *it->second;
         if (state) *state = r.state;
         if (status) *status = r.status;
         if (r.state == LDOPF_REQ_FAILED) fail(r.code, "request failed: " + r.detail);
@@ -414,9 +442,16 @@ int ldopf_server_destroy(ldopf_server* srv) {
             std::lock_guard<std::mutex> lk(srv->mu);
             srv->stop = true;
             // queued requests are dropped; running ones finish
-            for (int64_t id : srv->queue) srv->reqs[id]->state = LDOPF_REQ_FAILED;
+            for (int64_t id : srv->queue) {
+                Request& r = *srv->reqs[id];
+                r.code = LDOPF_INVALID_ARGUMENT;
+                r.detail = "dropped at shutdown";
+                r.state = LDOPF_REQ_FAILED;
+                srv->failed++;
+            }
             srv->queue.clear();
             srv->cv_work.notify_all();
+            srv->cv_done.notify_all();
         }
         if (srv->worker.joinable()) srv->worker.join();
         for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
