@@ -166,6 +166,8 @@ typedef struct ldopf_sizes {
     int32_t n_parts;    /* workgroups of the persistent sweep */
     int32_t block_threads;
     int64_t lds_bytes;  /* LDS per workgroup of the sweep */
+    int64_t sync_bytes; /* device bytes of the sweep's exchange words, residual sums and status
+                           (what ldopf_solve_noalloc takes from its static array) */
 } ldopf_sizes;
 
 typedef struct ldopf_status {
@@ -239,6 +241,25 @@ LDOPF_API int ldopf_set_options(ldopf_problem* h, const ldopf_options* opts);
  * Returns LDOPF_OK, LDOPF_NOT_CONVERGED, LDOPF_NUMERICAL or an error.
  */
 LDOPF_API int ldopf_solve(ldopf_problem* h, ldopf_status* status);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as ldopf_solve, from a handle created beforehand, with the sweep's
+ * synchronisation words (exchange words between workgroups, residual sums,
+ * status) taken from a static device array of 4 MiB that every GPU the
+ * library runs on holds until the process ends, instead of the handle's
+ * buffers. Calls no hipMalloc or hipFree and allocates no device memory.
+ * The residual history is recorded only into the buffer an earlier
+ * ldopf_solve on this handle allocated (rows beyond it are not recorded;
+ * none without one). Results equal ldopf_solve's bit for bit.
+ * Limit: ldopf_sizes.sync_bytes <= 4 MiB, else LDOPF_OUT_OF_MEMORY with
+ * nothing run. Every call on one GPU uses that GPU's one array, so calls
+ * that overlap on a GPU would race: this library serializes them (a second
+ * caller waits for the first to return). Runs on the handle's device and
+ * stream; blocks until done. Returns as ldopf_solve.
+ */
+LDOPF_API int ldopf_solve_noalloc(ldopf_problem* h, ldopf_status* status);
 
 /* Back to the initial point of Section V-A. */
 LDOPF_API int ldopf_reset(ldopf_problem* h);

@@ -63,6 +63,7 @@ class ldopf_sizes(C.Structure):
         ("n", C.c_int64), ("n_sub", C.c_int64), ("n_local", C.c_int64), ("sum_m", C.c_int64),
         ("op_words", C.c_int64), ("rank_words", C.c_int64), ("max_n", C.c_int32), ("max_m", C.c_int32),
         ("n_parts", C.c_int32), ("block_threads", C.c_int32), ("lds_bytes", C.c_int64),
+        ("sync_bytes", C.c_int64),
     ]
 
 
@@ -117,6 +118,7 @@ SIGNATURES = {
     "ldopf_get_sizes": (C.c_int, [C.c_void_p, C.POINTER(ldopf_sizes)]),
     "ldopf_set_options": (C.c_int, [C.c_void_p, C.POINTER(ldopf_options)]),
     "ldopf_solve": (C.c_int, [C.c_void_p, C.POINTER(ldopf_status)]),
+    "ldopf_solve_noalloc": (C.c_int, [C.c_void_p, C.POINTER(ldopf_status)]),
     "ldopf_reset": (C.c_int, [C.c_void_p]),
     "ldopf_warm_start": (C.c_int, [C.c_void_p, _d, _d, C.c_int64]),
     "ldopf_get_global": (C.c_int, [C.c_void_p, _d, C.c_int64]),

@@ -8,7 +8,9 @@
 #include <cstring>
 #include <exception>
 #include <new>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device.h"
@@ -68,6 +70,7 @@ void build_device(ldopf_problem& h) {
     hipStream_t s = h.stream;
     int dev = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
+    h.device = dev;
     int cus = 0, coop = 0, lds_optin = 0, clock_khz = 0;
     hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
     hip_check(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev), "device attribute");
@@ -259,20 +262,38 @@ ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipSt
     return h;
 }
 
-void problem_launch(ldopf_problem& h) {
+static_assert(sizeof(SweepStatus) <= 256, "the status word sits in the first 256 bytes of the scratch");
+
+size_t problem_sync_bytes(const ldopf_problem& h) {
+    const size_t w = h.fp32 ? 4 : 8;
+    const size_t nb = (size_t(2) * size_t(std::max(h.plan.n_slots, 1)) * w + 255) & ~size_t(255);
+    // status word, group sums, every part's sums, boundary words (each 256-aligned)
+    return 256 + size_t(kRing) * 8 * kGroup * 8 + size_t(kRing) * size_t(std::max(h.plan.n_parts, 1)) * 64 + nb;
+}
+
+void problem_launch(ldopf_problem& h, const SyncWords* sw) {
     if (h.in_flight) fail(LDOPF_INVALID_ARGUMENT, "a solve is already in flight on this handle");
-    const int64_t want = h.opts.history ? std::min<int64_t>(std::max<int64_t>(h.opts.max_iter, 1), int64_t(1) << 22) : 1;
-    if (int64_t(h.hist.count) < want * 4) h.hist.alloc(size_t(want) * 4, "history");
+    if (!sw) {
+        const int64_t want = h.opts.history ? std::min<int64_t>(std::max<int64_t>(h.opts.max_iter, 1), int64_t(1) << 22) : 1;
+        if (int64_t(h.hist.count) < want * 4) h.hist.alloc(size_t(want) * 4, "history");
+    }
     hipError_t e;
     hip_check(hipEventRecord(h.ev0, h.stream), "event");
-    if (h.fp32) {
-        e = launch_sweep(sweep_args<float>(h), h.plan.n_parts, h.plan.block_threads, size_t(h.plan.lds_bytes), h.stream);
-    } else {
-        e = launch_sweep(sweep_args<double>(h), h.plan.n_parts, h.plan.block_threads, size_t(h.plan.lds_bytes), h.stream);
-    }
+    auto launch = [&](auto args) {
+        using T = std::remove_pointer_t<decltype(args.bpart)>;
+        if (sw) {
+            args.bpart = static_cast<T*>(sw->bpart);
+            args.rpart = sw->rpart;
+            args.gpart = sw->gpart;
+            args.st = sw->st;
+        }
+        return launch_sweep(args, h.plan.n_parts, h.plan.block_threads, size_t(h.plan.lds_bytes), h.stream);
+    };
+    e = h.fp32 ? launch(sweep_args<float>(h)) : launch(sweep_args<double>(h));
     hip_check(e, "sweep launch");
     hip_check(hipEventRecord(h.ev1, h.stream), "event");
-    hip_check(hipMemcpyAsync(&h.last, h.st.p, sizeof(h.last), hipMemcpyDeviceToHost, h.stream), "download status");
+    hip_check(hipMemcpyAsync(&h.last, sw ? sw->st : h.st.p, sizeof(h.last), hipMemcpyDeviceToHost, h.stream),
+              "download status");
     hip_check(hipEventRecord(h.done, h.stream), "event");
     h.in_flight = true;
 }
@@ -498,6 +519,7 @@ int ldopf_get_sizes(const ldopf_problem* h, ldopf_sizes* o) {
         o->n_parts = h->plan.n_parts;
         o->block_threads = h->plan.block_threads;
         o->lds_bytes = h->plan.lds_bytes;
+        o->sync_bytes = int64_t(problem_sync_bytes(*h));
     });
 }
 
@@ -518,6 +540,56 @@ int ldopf_solve(ldopf_problem* h, ldopf_status* status) {
     const int rc = guard([&] {
         need(h, "handle");
         problem_launch(*h);
+        code = problem_finish(*h, status);
+    });
+    if (rc != LDOPF_OK && status) status->code = rc;
+    return rc != LDOPF_OK ? rc : code;
+}
+
+namespace {
+// One allocation-free solve at a time per GPU: they share its static array.
+std::mutex g_noalloc_mu[kMaxDevices];
+
+// Makes `dev` current for the scope of one call and restores the caller's.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        int cur = 0;
+        hip_check(hipGetDevice(&cur), "hipGetDevice");
+        if (cur != dev) {
+            hip_check(hipSetDevice(dev), "hipSetDevice");
+            prev = cur;
+        }
+    }
+    ~DeviceScope() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    DeviceScope(const DeviceScope&) = delete;
+    DeviceScope& operator=(const DeviceScope&) = delete;
+};
+}  // namespace
+
+int ldopf_solve_noalloc(ldopf_problem* h, ldopf_status* status) {
+    int code = LDOPF_OK;
+    const int rc = guard([&] {
+        need(h, "handle");
+        const size_t bytes = problem_sync_bytes(*h);
+        if (bytes > kStaticScratchBytes)
+            fail(LDOPF_OUT_OF_MEMORY, "the sweep needs " + std::to_string(bytes) + " bytes of synchronisation words; the static scratch holds " +
+                                          std::to_string(kStaticScratchBytes));
+        if (h->device < 0 || h->device >= kMaxDevices) fail(LDOPF_UNSUPPORTED, "device index out of range");
+        DeviceScope scope(h->device);
+        std::lock_guard<std::mutex> lock(g_noalloc_mu[h->device]);
+        void* base = nullptr;
+        hip_check(static_scratch(&base), "address of the static scratch");
+        unsigned char* p = static_cast<unsigned char*>(base);
+        const size_t P = size_t(std::max(h->plan.n_parts, 1));
+        SyncWords sw{};
+        sw.st = reinterpret_cast<SweepStatus*>(p);
+        sw.gpart = reinterpret_cast<double*>(p + 256);
+        sw.rpart = reinterpret_cast<double*>(p + 256 + size_t(kRing) * 8 * kGroup * 8);
+        sw.bpart = p + 256 + size_t(kRing) * 8 * kGroup * 8 + size_t(kRing) * P * 64;
+        problem_launch(*h, &sw);
         code = problem_finish(*h, status);
     });
     if (rc != LDOPF_OK && status) status->code = rc;

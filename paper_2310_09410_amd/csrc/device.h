@@ -85,6 +85,14 @@ struct SweepArgs {
     double* prof;        // nullable: per-phase wall-clock ticks of every workgroup ([P][8])
 };
 
+// Device memory of the allocation-free solve: the sweep's exchange words,
+// residual rings and status word come from one static array per GPU instead
+// of buffers of the handle. static_scratch gives its address on the current
+// device (looked up once per device, then remembered).
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(void** ptr);
+
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream);
 hipError_t prepare_sweep(bool fp32, size_t lds_bytes);
 hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu);

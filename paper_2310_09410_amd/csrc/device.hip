@@ -34,13 +34,45 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "internal.h"
 #include "layout.h"
 #include "device.h"
 #include "gs_core.h"
 
+// Synchronisation words of the allocation-free solve (ldopf_solve_noalloc):
+// every GPU the library runs on holds one copy until the process ends. Host
+// code never passes this name to a kernel: it is a host-side stand-in, and
+// the device address comes from hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[ldopf::kStaticScratchBytes];
+
 namespace ldopf {
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** ptr) {
+    *ptr = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        // once per device, with that device current: each GPU holds its own
+        // copy of the array at its own address
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 namespace {
 

@@ -26,6 +26,7 @@ struct ldopf_problem {
     ldopf_options opts{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = 0;  // the GPU the handle's buffers live on
     hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
     bool fp32 = false;
     Plan plan;
@@ -63,8 +64,20 @@ namespace ldopf {
 
 // Host LP -> handle with operators precomputed on the device (throws).
 ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipStream_t stream);
-// Enqueue one solve (from the current state) on the handle's stream.
-void problem_launch(ldopf_problem& h);
+// Where the sweep's synchronisation words live: the handle's own buffers,
+// or (allocation-free solve) carved from the static scratch array.
+struct SyncWords {
+    void* bpart;
+    double* rpart;
+    double* gpart;
+    SweepStatus* st;
+};
+// Device bytes of the synchronisation words of the handle's sweep.
+size_t problem_sync_bytes(const ldopf_problem& h);
+// Enqueue one solve (from the current state) on the handle's stream. With
+// sw, the sweep uses those words and nothing is allocated (the history goes
+// only into the buffer the handle already holds).
+void problem_launch(ldopf_problem& h, const SyncWords* sw = nullptr);
 // True when the enqueued solve has finished on the device.
 bool problem_ready(const ldopf_problem& h);
 // Wait for the enqueued solve, read its status; returns the ldopf_code.

@@ -134,6 +134,12 @@ class Problem:
         _check(code, "ldopf_solve", allow=(LDOPF_OK, LDOPF_NOT_CONVERGED))
         return st
 
+    def solve_noalloc(self) -> ldopf_status:
+        st = ldopf_status()
+        code = N.lib().ldopf_solve_noalloc(self.h, C.byref(st))
+        _check(code, "ldopf_solve_noalloc", allow=(LDOPF_OK, LDOPF_NOT_CONVERGED))
+        return st
+
     def reset(self):
         _check(N.lib().ldopf_reset(self.h), "ldopf_reset")
 
