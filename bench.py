@@ -117,50 +117,106 @@ def run_batched(P, L, make_feeder, scenario_factors, stream):
     return rec
 
 
-def run_serving(P, make_feeder, n_req: int, seed: int = 7):
-    """Poisson arrivals of solve requests on fresh feeders sized uniformly
-    from {13, 123, 2500, 8500} buses, FP32-mixed or FP64 with probability
-    1/2 each, at about 0.9 of a serial server's throughput."""
+def _serving_requests(make_feeder, n_req: int, seed: int, id0: int):
+    """n_req requests: feeder size uniform over {13, 123, 2500, 8500} buses,
+    a fresh feeder seed each (id0 + i), FP32-mixed or FP64 with probability
+    1/2 each."""
     import numpy as np
     rng = np.random.default_rng(seed)
     sizes = ["13", "123", "2500", "8500"]
-    est_s = {"13": 0.005, "123": 0.05, "2500": 1.1, "8500": 2.0}  # serial solve times, measured before
-    rate = 0.9 / (sum(est_s.values()) / 4)
-    plan = []
-    t = 0.0
+    out = []
     for i in range(n_req):
-        t += rng.exponential(1.0 / rate)
-        plan.append((t, sizes[int(rng.integers(0, 4))], int(rng.integers(0, 2)), 50000 + i))
-    nets = [(at, make_feeder(sz, sd), prec) for at, sz, prec, sd in plan]
+        sz = sizes[int(rng.integers(0, 4))]
+        out.append((sz, int(rng.integers(0, 2)), make_feeder(sz, id0 + i)))
+    return out
+
+
+def _serve(P, reqs, arrivals):
+    """Submit reqs at the given arrival times (seconds from the start; None:
+    all at once), wait for all, return the server's statistics."""
     srv = P.Server(max_slots=8)
     start = time.perf_counter()
     ids = []
-    for at, net, prec in nets:
-        while time.perf_counter() - start < at:
-            time.sleep(0.001)
+    for k, (_, prec, net) in enumerate(reqs):
+        if arrivals is not None:
+            while time.perf_counter() - start < arrivals[k]:
+                time.sleep(0.0005)
         ids.append(srv.submit(net, P.ldopf_default_options(precision=prec)))
     for rid in ids:
-        srv.wait(rid, 600)
+        srv.wait(rid, 1200)
     st = srv.stats()
     srv.close()
-    return {"workload": f"{n_req} Poisson requests (rate {rate:.2f}/s) on fresh 13/123/2500/8500-bus feeders, "
-                        "FP32-mixed or FP64 at random, to eps_rel 1e-4",
-            "solves_per_s": st.solves_per_s, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
-            "completed": st.completed, "failed": st.failed, "peak_in_flight": st.peak_running,
-            "peak_bytes": st.peak_bytes_in_use, "sizes": [p_[1] for p_ in plan]}
+    return st
+
+
+def run_serving(P, make_feeder, n_req: int, rate_fracs=(0.5, 0.9), seed: int = 7):
+    """The serving stream: first the saturated throughput (n_req requests
+    submitted at once), then Poisson arrivals of n_req fresh requests at each
+    fraction of that throughput; latency = completion - submit."""
+    import numpy as np
+
+    def stats(st):
+        return {"solves_per_s": st.solves_per_s, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
+                "max_ms": st.max_ms, "completed": st.completed, "failed": st.failed,
+                "peak_in_flight": st.peak_running, "peak_bytes": st.peak_bytes_in_use}
+
+    reqs = _serving_requests(make_feeder, n_req, seed, 50000)
+    sat = _serve(P, reqs, None)
+    mu = sat.completed / max(sat.wall_s, 1e-9)
+    progress(f"serving: saturated {mu:.2f} solves/s over {n_req} requests")
+    out = {"workload": f"{n_req} requests per phase on fresh 13/123/2500/8500-bus feeders (size uniform), "
+                       "FP32-mixed or FP64 at random, each to eps_rel 1e-4",
+           "sizes": {z: sum(1 for r in reqs if r[0] == z) for z in ("13", "123", "2500", "8500")},
+           "saturated": dict(stats(sat), arrivals="all at once"), "poisson": []}
+    for j, frac in enumerate(rate_fracs):
+        rate = frac * mu
+        rng = np.random.default_rng(seed + 1 + j)
+        arr = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        reqs = _serving_requests(make_feeder, n_req, seed + 100 + j, 60000 + 10000 * j)
+        st = _serve(P, reqs, arr)
+        out["poisson"].append(dict(stats(st), rate_fraction_of_saturated=frac, rate_per_s=rate))
+        progress(f"serving: Poisson at {frac} x saturated done (p99 {st.p99_ms:.0f} ms)")
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def cpu_baseline(sweeps: int) -> dict:
     """The FP64 oracle timed on this host: a bounded sample of sweeps of the
-    same feeder after its precompute. Runs in a child process pinned to one
-    BLAS/OpenMP thread so the core count is exact."""
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", str(sweeps)],
-                         env=env, capture_output=True, text=True, check=True)
-    return json.loads(out.stdout.strip().splitlines()[-1])
+    same feeder after its precompute, in a child process, once with one
+    BLAS/OpenMP thread (the reported value) and once with every host core
+    this process may run on available to BLAS/OpenMP."""
+    def child(threads: int) -> dict:
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads), OPENBLAS_NUM_THREADS=str(threads),
+                   MKL_NUM_THREADS=str(threads))
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", str(sweeps),
+                              "--cpu-threads", str(threads)], env=env, capture_output=True, text=True, check=True)
+        return json.loads(out.stdout.strip().splitlines()[-1])
+    one = child(1)
+    cores = _host_cores()
+    allc = child(cores)
+    one["cpu_model"] = _cpu_model()
+    one["nproc"] = cores
+    one["all_cores"] = {"value": allc["value"], "unit": allc["unit"], "cores": cores, "sample": allc["sample"]}
+    return one
 
 
-def _cpu_baseline_child(sweeps: int):
+def _cpu_baseline_child(sweeps: int, threads: int):
     from oracle import admm, model
     from synth import make_feeder
     net = make_feeder("8500", 8500)
@@ -168,9 +224,49 @@ def _cpu_baseline_child(sweeps: int):
     t0 = time.perf_counter()
     admm.solve(prep, max_iter=sweeps, check=False)
     dt = time.perf_counter() - t0
-    print(json.dumps({"value": sweeps / dt, "unit": "iter/s", "cores": 1, "kind": "oracle",
+    what = "one thread" if threads == 1 else f"{threads} BLAS/OpenMP threads allowed"
+    print(json.dumps({"value": sweeps / dt, "unit": "iter/s", "cores": threads, "kind": "oracle",
                       "sample": f"{sweeps} FP64 oracle sweeps (global, local, dual update and residuals) of the "
-                                f"same 8500-bus feeder after its precompute, {dt:.1f} s, one thread"}))
+                                f"same 8500-bus feeder after its precompute, {dt:.1f} s, {what}"}))
+
+
+def run_small(P, L, make_feeder, stream, steps: int = 5) -> dict:
+    """The 13- and 123-bus feeders to eps_rel 1e-4 in FP64: iterations, time
+    to tolerance and time per sweep. The 13-bus plan is one workgroup with no
+    exchange between workgroups, so its time per sweep is the floor that the
+    sweep's block barriers and residual-sum round trip set."""
+    out = {}
+    for name in ("13", "123"):
+        net = make_feeder(name, int(name))
+        prob = P.ldopf_create(net, P.ldopf_default_options(), stream=stream)
+        prob.solve()
+        kms, comp = [], 0
+        for _ in range(steps):
+            prob.reset()
+            st = prob.solve()
+            kms.append(st.sweep_ms)
+            comp += st.sweeps_computed
+        sz = prob.sizes()
+        out[name] = {"iterations_to_tol": st.iterations, "time_to_tol_ms": sum(kms) / len(kms),
+                     "us_per_sweep": 1e3 * sum(kms) / comp, "workgroups": sz.n_parts,
+                     "block_threads": sz.block_threads, "objective": prob.objective()}
+        prob.close()
+    return out
+
+
+def phase_profile(P, net, stream, sweeps: int = 20000) -> dict:
+    """Per-phase wall-clock time of one workgroup of the 8500-bus sweep
+    (profiled build of the kernel, fixed sweeps), in us per sweep."""
+    prob = P.ldopf_create(net, P.ldopf_default_options(max_iter=sweeps, check_termination=0, profile=1),
+                          stream=stream)
+    st = prob.solve()
+    ms = prob.get_phase_times(0)
+    prob.close()
+    k = 1e3 / max(1, st.sweeps_computed)
+    return {"sweeps": st.sweeps_computed, "us_per_sweep_profiled": 1e3 * st.sweep_ms / max(1, st.sweeps_computed),
+            "global_update_and_exchange_wait": ms[0] * k, "own_global_update": ms[7] * k,
+            "gather": ms[1] * k, "t_eq_W_v": ms[2] * k, "local_dual_residual_sums": ms[3] * k,
+            "publish": ms[4] * k, "termination_test_wave": ms[6] * k}
 
 
 def main():
@@ -183,15 +279,19 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=12)
+    ap.add_argument("--serving-requests", type=int, default=16, help="requests per serving phase")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving stream (saturated, then Poisson at 0.5 and 0.9 of it)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="one copy of known size and one solve, for rocprofv3 counter runs")
     ap.add_argument("--profile-batched", type=int, default=0, metavar="SWEEPS",
                     help="only the batched workload: tune, then SWEEPS fixed sweeps, for rocprofv3 runs")
     ap.add_argument("--cpu-baseline-only", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-threads", type=int, default=1, help=argparse.SUPPRESS)
+    ap.add_argument("--no-small", action="store_true")
     args = ap.parse_args()
     if args.cpu_baseline_only:
-        _cpu_baseline_child(args.cpu_baseline_only)
+        _cpu_baseline_child(args.cpu_baseline_only, args.cpu_threads)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -222,6 +322,10 @@ def main():
                           "bytes_per_batched_sweep": batched_bytes_per_sweep(bs),
                           "achieved_GBs": batched_bytes_per_sweep(bs) / (us * 1e-6) / 1e9}))
         b.close()
+        return
+
+    if args.serving_only:
+        print(json.dumps({"serving": run_serving(P, make_feeder, args.serving_requests)}))
         return
 
     if args.profile_pass:
@@ -289,9 +393,20 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
                      "kernel": "sweep_kernel<double> (one persistent launch per solve)",
                      "bytes_per_sweep": b_sweep, "sweeps_per_launch": sweeps_per_launch,
-                     "launch_ms": launch_ms},
+                     "launch_ms": launch_ms,
+                     "achieved_is": "algorithmic bytes per sweep / time per sweep (operators and state stay in LDS)",
+                     "measured_hbm_GBs": None, "limiter": "exchange latency between workgroups, block barriers "
+                                                          "and dependent LDS reads, not HBM bandwidth"},
     }
+    if rec["roofline"]["traffic"] is not None:
+        rec["roofline"]["measured_hbm_GBs"] = rec["roofline"]["traffic"] / (launch_ms * 1e-3) / 1e9
     prob.close()
+    if not args.no_small:
+        rec["small_feeders"] = run_small(P, L, make_feeder, stream)
+        rec["sync_floor"] = {"us_per_sweep_13bus_one_workgroup": rec["small_feeders"]["13"]["us_per_sweep"],
+                             "us_per_sweep_8500bus": rec["us_per_sweep"],
+                             "phase_us_8500bus_workgroup0": phase_profile(P, net, stream)}
+        progress("small feeders and phase profile done")
     if not args.no_fp32:
         p32, st32, it32, c32, k32, dt32 = run(L.LDOPF_FP32_MIXED)
         progress(f"fp32-mixed: {args.steps} solves in {dt32:.2f} s")

@@ -88,10 +88,26 @@ typedef enum ldopf_residual_form {
     /* Section III-C taken literally: dres = rho * ||x_s - x_s_prev|| and
      * eps_dual = eps_rel * ||lambda|| over all local copies */
     LDOPF_RESIDUAL_PAPER = 0,
-    /* textbook form with sum_s B_s' applied before the norm (oracle only in
-     * this build; the device path returns LDOPF_UNSUPPORTED) */
+    /* textbook form with sum_s B_s' applied before the norm: per global
+     * variable the sums over its copies, dres = rho * ||sum_s B_s' (x_s -
+     * x_s_prev)||, eps_dual = eps_rel * ||sum_s B_s' lambda_s|| (and
+     * sqrt(n) * eps_abs instead of sqrt(N_loc) * eps_abs) */
     LDOPF_RESIDUAL_AGGREGATED = 1
 } ldopf_residual_form;
+
+typedef enum ldopf_rho_update {
+    /* rho fixed for the whole solve (Algorithm 1) */
+    LDOPF_RHO_FIXED = 0,
+    /* residual balancing (one of the acceleration schemes Section III-D
+     * names; rule of He et al. 2000 / Boyd et al. 2011 on relative
+     * residuals as in Wohlberg 2017): after every sweep t that is a multiple
+     * of rho_period, with r = pres / eps_prim and s = dres / eps_dual,
+     * rho is multiplied by rho_tau if r > rho_mu * s and divided by it if
+     * s > rho_mu * r; the new rho is used from sweep t + 4 on; at most
+     * rho_max_changes changes. lambda (unscaled) is kept; Abar_s and bbar_s
+     * do not depend on rho, so nothing is recomputed. */
+    LDOPF_RHO_BALANCE = 1
+} ldopf_rho_update;
 
 /*
  * Network data (nomenclature table of Section II). Structure of arrays,
@@ -152,7 +168,12 @@ typedef struct ldopf_options {
     int32_t block_threads;   /* tuning: threads per workgroup (128..1024, multiple of 64: row waves plus the
                                 wave that runs the termination test); 0 = automatic */
     int32_t profile;         /* 1: record per-phase device time of the sweep (ldopf_get_phase_times); default 0 */
-    int32_t reserved[5];     /* must be zero */
+    int32_t rho_update;      /* ldopf_rho_update; default LDOPF_RHO_FIXED */
+    int32_t rho_period;      /* residual balancing: sweeps between evaluations of the rule (>= 4); default 100 */
+    int32_t rho_max_changes; /* residual balancing: changes at most (0..1024); default 16 */
+    int32_t reserved[2];     /* must be zero */
+    double rho_mu;           /* residual balancing: imbalance that triggers a change (> 1); default 10 */
+    double rho_tau;          /* residual balancing: factor of a change (> 1); default 2 */
 } ldopf_options;
 
 typedef struct ldopf_sizes {
@@ -180,6 +201,8 @@ typedef struct ldopf_status {
     int64_t sweeps_computed; /* sweeps the kernel ran: the test of a sweep is evaluated while the
                                 next one runs, so a converged solve computes one sweep more than
                                 it returns */
+    double rho;           /* rho of the returned sweep */
+    int64_t rho_changes;  /* changes of rho made by residual balancing in this solve */
 } ldopf_status;
 
 typedef struct ldopf_problem ldopf_problem;
@@ -265,7 +288,8 @@ LDOPF_API int ldopf_solve_noalloc(ldopf_problem* h, ldopf_status* status);
 LDOPF_API int ldopf_reset(ldopf_problem* h);
 
 /* Continue from a given state: x_s and lambda [N_loc] in local-copy order.
- * A following ldopf_solve resumes exactly as if the sweeps had not stopped. */
+ * A following ldopf_solve resumes exactly as if the sweeps had not stopped.
+ * A NaN or Inf entry is refused with LDOPF_NUMERICAL (nothing is uploaded). */
 LDOPF_API int ldopf_warm_start(ldopf_problem* h, const double* xs, const double* lam, int64_t n_local);
 
 /* Global x [n] of the last sweep (NaN before the first sweep). */
@@ -281,6 +305,10 @@ LDOPF_API int ldopf_get_history(const ldopf_problem* h, double* hist, int64_t ca
  * bbar [N_loc], numerical rank of each A_s [S]; any pointer may be NULL. */
 LDOPF_API int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t cap_abar,
                                   double* bbar, int64_t cap_bbar, int32_t* rank, int64_t cap_rank);
+/* The changes of rho residual balancing made in the last solve: the first
+ * sweep that used each new value and the value; *len = the number of
+ * changes; writes min(len, cap) entries (either array may be NULL). */
+LDOPF_API int ldopf_get_rho_log(const ldopf_problem* h, int64_t* sweeps, double* rhos, int64_t cap, int64_t* len);
 /* Per-phase device time of the last solve with options.profile = 1, in ms,
  * measured by workgroup 0 with the wall clock: [0] global update, with the
  * wait for the neighbours' partial sums, [1] gather of B_s x + lambda/rho,

@@ -181,6 +181,57 @@ def residuals(prep: Prepared, z, xs, xs_prev, lam, rho, eps_rel, eps_abs, form):
 
 
 @dataclasses.dataclass
+class RhoBalance:
+    """Residual balancing of the penalty rho.
+
+    Section III-D names residual balancing among the acceleration schemes
+    that combine with the method, without fixing a rule. The rule here is
+    the classic one (He, Yang and Wang 2000; Boyd et al. 2011, Section
+    3.4.1) on relative residuals, as Wohlberg (2017) recommends: after sweep
+    t, with r = pres / eps_prim and s = dres / eps_dual (the two ratios of
+    the termination test of Section III-C),
+      rho <- tau * rho  if r > mu * s,   rho <- rho / tau  if s > mu * r.
+    The rule is evaluated after the sweeps that are multiples of `period`,
+    the new rho is used from sweep t + lag on, and at most `max_changes`
+    changes are made (after that rho stays fixed, so the usual convergence
+    argument of ADMM applies to the rest of the run). lambda is the unscaled
+    dual of B_s x = x_s and is kept as it is when rho changes (only a scaled
+    dual lambda / rho would need rescaling); Abar_s and bbar_s do not depend
+    on rho, so nothing is recomputed.
+    """
+    mu: float = 10.0
+    tau: float = 2.0
+    period: int = 100
+    lag: int = 4
+    max_changes: int = 16
+
+    def __post_init__(self):
+        if not (self.mu > 1.0 and self.tau > 1.0 and self.lag >= 1 and self.period >= self.lag
+                and self.max_changes >= 0):
+            raise ValueError("need mu > 1, tau > 1, lag >= 1, period >= lag, max_changes >= 0")
+
+
+def rescale_dual(lam: np.ndarray, rho_old: float, rho_new: float) -> np.ndarray:
+    """What a change of rho does to the dual: nothing. lambda_s is the
+    unscaled multiplier of B_s x = x_s in ADMM-1..3; only the scaled form
+    u = lambda / rho would be rescaled, by rho_old / rho_new."""
+    return lam
+
+
+def balance_factor(rule: RhoBalance, pres, dres, eps_p, eps_d) -> float:
+    """The factor the residual-balancing rule applies to rho after a sweep
+    (1 when neither relative residual dominates or a tolerance is zero)."""
+    if eps_p <= 0.0 or eps_d <= 0.0:
+        return 1.0
+    r, s = pres / eps_p, dres / eps_d
+    if r > rule.mu * s:
+        return rule.tau
+    if s > rule.mu * r:
+        return 1.0 / rule.tau
+    return 1.0
+
+
+@dataclasses.dataclass
 class Result:
     x: np.ndarray
     xs: np.ndarray
@@ -190,34 +241,48 @@ class Result:
     converged: bool
     objective: float
     prep: Prepared
+    rho: float = 0.0  # rho of the last sweep
+    rho_log: list = dataclasses.field(default_factory=list)  # (first sweep, rho) of every change
 
 
 def solve(lp_or_prep, rho: float = 100.0, eps_rel: float = 1e-4, eps_abs: float = 0.0,
           max_iter: int = 1_000_000, check: bool = True, form: str = "paper",
-          state: State | None = None, on_iter=None) -> Result:
+          state: State | None = None, on_iter=None, balance: RhoBalance | None = None) -> Result:
     """Run Algorithm 1 until the termination test holds (or ``max_iter`` sweeps).
 
     ``check=False`` runs exactly ``max_iter`` sweeps. ``on_iter(t, prep, state)``
     is called after every sweep (tests use it to check invariants).
+    ``balance``: residual balancing of rho (RhoBalance); None keeps rho fixed.
     """
     prep = lp_or_prep if isinstance(lp_or_prep, Prepared) else prepare(lp_or_prep)
     st = state if state is not None else initial_state(prep)
     x, xs, lam = st.x, st.xs.copy(), st.lam.copy()
     hist = []
     converged = False
+    scheduled = {}  # sweep -> rho from that sweep on
+    rho_log = []
     t = 0
     while t < max_iter:
+        t += 1
+        if t in scheduled:
+            rho_new = scheduled.pop(t)
+            lam = rescale_dual(lam, rho, rho_new)
+            rho = rho_new
+            rho_log.append((t, rho))
         x = global_update(prep, xs, lam, rho)
         z, xs_new = local_update(prep, x, lam, rho)
         lam = dual_update(lam, z, xs_new, rho)
         r = residuals(prep, z, xs_new, xs, lam, rho, eps_rel, eps_abs, form)
         xs = xs_new
         hist.append(r)
-        t += 1
         if on_iter is not None:
             on_iter(t, prep, State(x, xs, lam))
         if check and r[0] <= r[2] and r[1] <= r[3]:
             converged = True
             break
+        if balance is not None and t % balance.period == 0 and len(rho_log) + len(scheduled) < balance.max_changes:
+            f = balance_factor(balance, *r)
+            if f != 1.0:
+                scheduled[t + balance.lag] = rho * f
     H = np.array(hist, dtype=np.float64).reshape(-1, 4)
-    return Result(x, xs, lam, H, t, converged, float(prep.lp.c @ x), prep)
+    return Result(x, xs, lam, H, t, converged, float(prep.lp.c @ x), prep, rho, rho_log)

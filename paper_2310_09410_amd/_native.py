@@ -27,6 +27,8 @@ LDOPF_FP64 = 0
 LDOPF_FP32_MIXED = 1
 LDOPF_RESIDUAL_PAPER = 0
 LDOPF_RESIDUAL_AGGREGATED = 1
+LDOPF_RHO_FIXED = 0
+LDOPF_RHO_BALANCE = 1
 
 _d = C.POINTER(C.c_double)
 _i32 = C.POINTER(C.c_int32)
@@ -54,7 +56,9 @@ class ldopf_options(C.Structure):
         ("rho", C.c_double), ("eps_rel", C.c_double), ("eps_abs", C.c_double), ("max_iter", C.c_int64),
         ("precision", C.c_int32), ("residual_form", C.c_int32), ("check_termination", C.c_int32),
         ("history", C.c_int32), ("rows_per_part", C.c_int32), ("block_threads", C.c_int32),
-        ("profile", C.c_int32), ("reserved", C.c_int32 * 5),
+        ("profile", C.c_int32), ("rho_update", C.c_int32), ("rho_period", C.c_int32),
+        ("rho_max_changes", C.c_int32), ("reserved", C.c_int32 * 2), ("rho_mu", C.c_double),
+        ("rho_tau", C.c_double),
     ]
 
 
@@ -72,6 +76,7 @@ class ldopf_status(C.Structure):
         ("iterations", C.c_int64), ("converged", C.c_int32), ("code", C.c_int32),
         ("pres", C.c_double), ("dres", C.c_double), ("eps_prim", C.c_double), ("eps_dual", C.c_double),
         ("sweep_ms", C.c_double), ("precompute_ms", C.c_double), ("sweeps_computed", C.c_int64),
+        ("rho", C.c_double), ("rho_changes", C.c_int64),
     ]
 
 
@@ -126,6 +131,7 @@ SIGNATURES = {
     "ldopf_get_structure": (C.c_int, [C.c_void_p, _i64, C.c_int64, _i64, C.c_int64]),
     "ldopf_get_history": (C.c_int, [C.c_void_p, _d, C.c_int64, _i64]),
     "ldopf_get_operators": (C.c_int, [C.c_void_p, _d, C.c_int64, _d, C.c_int64, _i32, C.c_int64]),
+    "ldopf_get_rho_log": (C.c_int, [C.c_void_p, _i64, _d, C.c_int64, _i64]),
     "ldopf_get_phase_times": (C.c_int, [C.c_void_p, _d]),
     "ldopf_get_phase_times_part": (C.c_int, [C.c_void_p, C.c_int32, _d]),
     "ldopf_objective": (C.c_int, [C.c_void_p, _d]),

@@ -33,9 +33,16 @@ void check_options(const ldopf_options& o) {
     if (!(o.eps_abs >= 0.0) || !std::isfinite(o.eps_abs)) fail(LDOPF_INVALID_ARGUMENT, "eps_abs must be >= 0");
     if (o.max_iter < 0) fail(LDOPF_INVALID_ARGUMENT, "max_iter must be >= 0");
     if (o.precision != LDOPF_FP64 && o.precision != LDOPF_FP32_MIXED) fail(LDOPF_INVALID_ARGUMENT, "unknown precision");
-    if (o.residual_form == LDOPF_RESIDUAL_AGGREGATED)
-        fail(LDOPF_UNSUPPORTED, "the aggregated residual form is not implemented on the device");
-    if (o.residual_form != LDOPF_RESIDUAL_PAPER) fail(LDOPF_INVALID_ARGUMENT, "unknown residual form");
+    if (o.residual_form != LDOPF_RESIDUAL_PAPER && o.residual_form != LDOPF_RESIDUAL_AGGREGATED)
+        fail(LDOPF_INVALID_ARGUMENT, "unknown residual form");
+    if (o.rho_update != LDOPF_RHO_FIXED && o.rho_update != LDOPF_RHO_BALANCE) fail(LDOPF_INVALID_ARGUMENT, "unknown rho_update");
+    if (o.rho_update == LDOPF_RHO_BALANCE) {
+        if (o.rho_period < kRhoLag) fail(LDOPF_INVALID_ARGUMENT, "rho_period must be >= 4 (a change takes effect 4 sweeps later)");
+        if (o.rho_max_changes < 0 || o.rho_max_changes > kMaxRhoChanges)
+            fail(LDOPF_INVALID_ARGUMENT, "rho_max_changes must be in [0, 1024]");
+        if (!(o.rho_mu > 1.0) || !std::isfinite(o.rho_mu)) fail(LDOPF_INVALID_ARGUMENT, "rho_mu must be > 1 and finite");
+        if (!(o.rho_tau > 1.0) || !std::isfinite(o.rho_tau)) fail(LDOPF_INVALID_ARGUMENT, "rho_tau must be > 1 and finite");
+    }
     if (o.check_termination != 0 && o.check_termination != 1) fail(LDOPF_INVALID_ARGUMENT, "check_termination must be 0 or 1");
     if (o.history != 0 && o.history != 1) fail(LDOPF_INVALID_ARGUMENT, "history must be 0 or 1");
     if (o.profile != 0 && o.profile != 1) fail(LDOPF_INVALID_ARGUMENT, "profile must be 0 or 1");
@@ -44,6 +51,12 @@ void check_options(const ldopf_options& o) {
         fail(LDOPF_INVALID_ARGUMENT, "block_threads must be 0 or a multiple of 64 in [128, 1024]");
     for (int r : o.reserved)
         if (r != 0) fail(LDOPF_INVALID_ARGUMENT, "reserved option fields must be zero");
+}
+
+void check_batch_options(const ldopf_options& o) {
+    if (o.residual_form != LDOPF_RESIDUAL_PAPER)
+        fail(LDOPF_UNSUPPORTED, "batched scenarios use the literal residual form of Section III-C");
+    if (o.rho_update != LDOPF_RHO_FIXED) fail(LDOPF_UNSUPPORTED, "batched scenarios keep rho fixed");
 }
 
 }  // namespace ldopf
@@ -173,6 +186,7 @@ void build_device(ldopf_problem& h) {
     h.rpart.alloc(size_t(kRing) * pl.n_parts * 8, "residual slots");
     h.gpart.alloc(size_t(kRing) * 8 * kGroup, "residual group slots");
     h.st.alloc(1, "status");
+    h.rholog.alloc(size_t(2) * kMaxRhoChanges, "rho log");
     h.prof.alloc(size_t(8) * std::max(pl.n_parts, 1), "phase times");
     init_state(h);
 }
@@ -213,6 +227,14 @@ SweepArgs<T> sweep_args(ldopf_problem& h) {
     a.eps_abs = h.opts.eps_abs;
     a.max_iter = h.opts.max_iter;
     a.nloc = int64_t(h.lp.gidx.size());
+    a.n = h.lp.n;
+    a.rho_update = h.opts.rho_update;
+    a.rho_period = std::max(h.opts.rho_period, 1);
+    a.rho_max_changes = h.opts.rho_update ? h.opts.rho_max_changes : 0;
+    a.rho_mu = h.opts.rho_mu;
+    a.rho_tau = h.opts.rho_tau;
+    a.rho_log = h.rholog.p;
+    a.bagg = h.opts.residual_form == LDOPF_RESIDUAL_AGGREGATED ? h.bagg.p : nullptr;
     a.n_slots = h.plan.n_slots;
     a.check = h.opts.check_termination;
     a.P = h.plan.n_parts;
@@ -264,11 +286,19 @@ ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipSt
 
 static_assert(sizeof(SweepStatus) <= 256, "the status word sits in the first 256 bytes of the scratch");
 
+namespace {
+size_t agg_words(const ldopf_problem& h) {
+    return h.opts.residual_form == LDOPF_RESIDUAL_AGGREGATED ? size_t(4) * size_t(std::max(h.plan.n_slots, 1)) : 0;
+}
+}  // namespace
+
 size_t problem_sync_bytes(const ldopf_problem& h) {
     const size_t w = h.fp32 ? 4 : 8;
     const size_t nb = (size_t(2) * size_t(std::max(h.plan.n_slots, 1)) * w + 255) & ~size_t(255);
-    // status word, group sums, every part's sums, boundary words (each 256-aligned)
-    return 256 + size_t(kRing) * 8 * kGroup * 8 + size_t(kRing) * size_t(std::max(h.plan.n_parts, 1)) * 64 + nb;
+    // status word, group sums, every part's sums, boundary words (each
+    // 256-aligned), then the aggregated form's boundary words
+    return 256 + size_t(kRing) * 8 * kGroup * 8 + size_t(kRing) * size_t(std::max(h.plan.n_parts, 1)) * 64 + nb +
+           agg_words(h) * 8;
 }
 
 void problem_launch(ldopf_problem& h, const SyncWords* sw) {
@@ -276,6 +306,7 @@ void problem_launch(ldopf_problem& h, const SyncWords* sw) {
     if (!sw) {
         const int64_t want = h.opts.history ? std::min<int64_t>(std::max<int64_t>(h.opts.max_iter, 1), int64_t(1) << 22) : 1;
         if (int64_t(h.hist.count) < want * 4) h.hist.alloc(size_t(want) * 4, "history");
+        if (h.bagg.count < agg_words(h)) h.bagg.alloc(agg_words(h), "aggregated residual words");
     }
     hipError_t e;
     hip_check(hipEventRecord(h.ev0, h.stream), "event");
@@ -285,6 +316,7 @@ void problem_launch(ldopf_problem& h, const SyncWords* sw) {
             args.bpart = static_cast<T*>(sw->bpart);
             args.rpart = sw->rpart;
             args.gpart = sw->gpart;
+            args.bagg = sw->bagg;
             args.st = sw->st;
         }
         return launch_sweep(args, h.plan.n_parts, h.plan.block_threads, size_t(h.plan.lds_bytes), h.stream);
@@ -337,6 +369,8 @@ int problem_finish(ldopf_problem& h, ldopf_status* status) {
         status->sweep_ms = ms;
         status->precompute_ms = h.precompute_ms;
         status->sweeps_computed = st.computed;
+        status->rho = st.rho;
+        status->rho_changes = st.rho_changes;
         status->code = code;
     }
     return code;
@@ -399,6 +433,11 @@ void ldopf_default_options(ldopf_options* o) {
     o->residual_form = LDOPF_RESIDUAL_PAPER;
     o->check_termination = 1;
     o->history = 1;
+    o->rho_update = LDOPF_RHO_FIXED;
+    o->rho_period = 100;
+    o->rho_max_changes = 16;
+    o->rho_mu = 10.0;
+    o->rho_tau = 2.0;
 }
 
 int ldopf_describe_network(const ldopf_network* net, int64_t sizes[5], double* c, double* lo, double* hi,
@@ -589,6 +628,9 @@ int ldopf_solve_noalloc(ldopf_problem* h, ldopf_status* status) {
         sw.gpart = reinterpret_cast<double*>(p + 256);
         sw.rpart = reinterpret_cast<double*>(p + 256 + size_t(kRing) * 8 * kGroup * 8);
         sw.bpart = p + 256 + size_t(kRing) * 8 * kGroup * 8 + size_t(kRing) * P * 64;
+        const size_t w = h->fp32 ? 4 : 8;
+        const size_t nb = (size_t(2) * size_t(std::max(h->plan.n_slots, 1)) * w + 255) & ~size_t(255);
+        sw.bagg = agg_words(*h) ? reinterpret_cast<double*>(static_cast<unsigned char*>(sw.bpart) + nb) : nullptr;
         problem_launch(*h, &sw);
         code = problem_finish(*h, status);
     });
@@ -610,7 +652,8 @@ int ldopf_warm_start(ldopf_problem* h, const double* xs, const double* lam, int6
         need(lam, "lam");
         if (n_local != int64_t(h->lp.gidx.size())) fail(LDOPF_INVALID_ARGUMENT, "n_local does not match the problem");
         for (int64_t k = 0; k < n_local; ++k)
-            if (!std::isfinite(xs[k]) || !std::isfinite(lam[k])) fail(LDOPF_INVALID_ARGUMENT, "non-finite warm-start value");
+            if (!std::isfinite(xs[k]) || !std::isfinite(lam[k]))
+                fail(LDOPF_NUMERICAL, "non-finite warm-start value at local copy " + std::to_string(k));
         hip_check(hipMemcpyAsync(h->xs.p, xs, n_local * 8, hipMemcpyHostToDevice, h->stream), "upload x_s");
         hip_check(hipMemcpyAsync(h->lam.p, lam, n_local * 8, hipMemcpyHostToDevice, h->stream), "upload lambda");
         hip_check(hipStreamSynchronize(h->stream), "warm start");
@@ -686,6 +729,24 @@ int ldopf_get_operators(const ldopf_problem* h, double* abar, int64_t cap_abar, 
             std::memcpy(rank, h->rank.data(), h->lp.S * 4);
         }
         hip_check(hipStreamSynchronize(h->stream), "download operators");
+    });
+}
+
+int ldopf_get_rho_log(const ldopf_problem* h, int64_t* sweeps, double* rhos, int64_t cap, int64_t* len) {
+    return guard([&] {
+        need(h, "handle");
+        need(len, "len");
+        const int64_t n = std::min<int64_t>(h->last.rho_changes, kMaxRhoChanges);
+        *len = n;
+        const int64_t k = std::min(n, std::max<int64_t>(cap, 0));
+        if (k == 0 || (!sweeps && !rhos)) return;
+        std::vector<double> log(size_t(2) * k);
+        hip_check(hipMemcpyAsync(log.data(), h->rholog.p, log.size() * 8, hipMemcpyDeviceToHost, h->stream), "download rho log");
+        hip_check(hipStreamSynchronize(h->stream), "download rho log");
+        for (int64_t i = 0; i < k; ++i) {
+            if (sweeps) sweeps[i] = int64_t(log[2 * i]);
+            if (rhos) rhos[i] = log[2 * i + 1];
+        }
     });
 }
 

@@ -815,6 +815,7 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
         ldopf_default_options(&o);
         if (opts) o = *opts;
         check_options(o);
+        check_batch_options(o);
         if (o.precision != LDOPF_FP32_MIXED)
             fail(LDOPF_UNSUPPORTED, "batched scenarios run in the FP32-mixed form (FP32 sweep, FP64 precompute and residuals)");
         ConsensusLP lp = assemble_network(*net);
@@ -1265,6 +1266,7 @@ int ldopf_batch_set_options(ldopf_batch* h, const ldopf_options* opts) {
         need(h, "handle");
         need(opts, "opts");
         check_options(*opts);
+        check_batch_options(*opts);
         if (opts->precision != h->opts.precision) fail(LDOPF_INVALID_ARGUMENT, "precision is fixed at creation");
         if (opts->rho != h->opts.rho) fail(LDOPF_INVALID_ARGUMENT, "rho is fixed at creation for a batch");
         h->opts = *opts;

@@ -37,12 +37,21 @@ constexpr int kGroup = 16;
 // Parts the sweep can run: kGroup groups of kGroup parts.
 constexpr int kMaxParts = kGroup * kGroup;
 
+// Residual balancing: a change of rho decided from the test of sweep t is
+// used from sweep t + kRhoLag on (the test of sweep t is read during sweep
+// t + 3, and the partial sums published in that sweep already feed sweep
+// t + 4's global update).
+constexpr int kRhoLag = 4;
+constexpr int kMaxRhoChanges = 1024;
+
 struct SweepStatus {
     int64_t iters;     // sweep whose state is returned
     int64_t computed;  // sweeps computed (the test of a sweep is read during the next one)
     int32_t converged;
     int32_t flags;  // 1: an exchange wait timed out, 2: non-finite residuals
     double pres, dres, eps_p, eps_d;
+    double rho;           // rho of the returned sweep
+    int64_t rho_changes;  // changes made by residual balancing
 };
 
 template <typename T>
@@ -78,11 +87,20 @@ struct SweepArgs {
     double rho, eps_rel, eps_abs;
     int64_t max_iter;
     int64_t nloc;
+    int64_t n;           // global variables (dimension of the aggregated dual residual)
     int64_t n_slots;
     int32_t check;
     int32_t P;
     uint64_t spin_limit; // wall-clock ticks an exchange wait may take
     double* prof;        // nullable: per-phase wall-clock ticks of every workgroup ([P][8])
+    // residual balancing of rho (rho_update != 0)
+    int32_t rho_update, rho_period, rho_max_changes;
+    double rho_mu, rho_tau;
+    double* rho_log;     // [rho_max_changes][2]: first sweep, rho (written by workgroup 0)
+    // aggregated residual form: boundary variables' per-owner sums of
+    // rho (x_s - x_s_prev) and of lambda over their copies, sent to owner 0
+    // ([2 parities][2 quantities][n_slots] doubles); null in the paper form
+    double* bagg;
 };
 
 // Device memory of the allocation-free solve: the sweep's exchange words,

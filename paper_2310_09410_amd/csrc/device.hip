@@ -236,12 +236,26 @@ __device__ inline uint32_t in_vgpr(uint32_t x) {
     asm volatile("" : "+v"(x));
     return x;
 }
+__device__ inline double in_vgpr(double x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ inline float in_vgpr(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
 
-template <typename T, bool PROF>
+template <typename T, bool PROF, bool AGG>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int ok_lds;
     __shared__ int test_lds;  // 1 stop, 2 converged, 4 non-finite: the last test
+    __shared__ double rho_of[8];  // rho of sweep k in entry k % 8 (residual balancing)
+    // the rule's parameters, read only where it is evaluated (kept out of
+    // the scalar registers, the scarce file of this kernel)
+    __shared__ double rule_mu, rule_tau;
+    __shared__ int rule_period, rule_max;
+    __shared__ double* rule_log;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const PartInfo pi = a.parts[blockIdx.x];
     const LdsLayout L = lds_layout(sizeof(T), uint32_t(pi.w_words), uint32_t(pi.n_row), uint32_t(pi.n_tk),
@@ -258,7 +272,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     T* vb = reinterpret_cast<T*>(smem + in_vgpr(L.v));
     T* tb = reinterpret_cast<T*>(smem + in_vgpr(L.t));
     T* ownp = reinterpret_cast<T*>(smem + in_vgpr(L.ownp));
-    T* crho = reinterpret_cast<T*>(smem + in_vgpr(L.crho));
+    T* cvar = reinterpret_cast<T*>(smem + in_vgpr(L.crho));  // c of each variable
     T* vlo = reinterpret_cast<T*>(smem + in_vgpr(L.lo));
     T* vhi = reinterpret_cast<T*>(smem + in_vgpr(L.hi));
     T* vcnt = reinterpret_cast<T*>(smem + in_vgpr(L.cnt));
@@ -275,10 +289,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     uint2* rwm = reinterpret_cast<uint2*>(smem + in_vgpr(L.row_m));
     uint16_t* vr0 = reinterpret_cast<uint16_t*>(smem + in_vgpr(L.var_r0));
     double* red = reinterpret_cast<double*>(smem + in_vgpr(L.red));
+    double* aggw = reinterpret_cast<double*>(smem + in_vgpr(L.agg));
     double* tot = red + 32 * nw;  // after the row sums [waves][4][8]
 
-    const T rho = T(a.rho);
-    const T irho = T(1.0 / a.rho);
+    // rho of the sweep being computed (sweep done + 1) and 1/rho of the next
+    // one, whose global update the partial sums published in this sweep feed
+    // (they differ only where residual balancing changes rho)
+    double rho_c = in_vgpr(a.rho);
+    T rho_cT = in_vgpr(T(a.rho)), irho_c = in_vgpr(T(1.0 / a.rho)), irho_n = irho_c;
     const int R = pi.n_row, V = pi.n_var, TK = pi.n_tk;
     const unsigned P = unsigned(a.P);
     const int64_t ns = a.n_slots;
@@ -286,6 +304,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
 
     // ---- load this part into LDS
     if (tid == 0) ok_lds = 1;
+    if (tid < 8) rho_of[tid] = a.rho;
+    if (tid == 0) {
+        rule_mu = a.rho_mu;
+        rule_tau = a.rho_tau;
+        rule_period = a.rho_update ? a.rho_period : 0;
+        rule_max = a.rho_update ? a.rho_max_changes : 0;
+        rule_log = a.rho_log;
+    }
     for (int i = tid; i < pi.n_sub; i += nt) {
         const SubMeta m = a.subs[pi.sub_begin + i];
         meta[i] = SubLds{m.row0, m.n, m.k, m.t0, m.mode, m.w0, 0u};
@@ -302,7 +328,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     for (int v = tid; v <= V; v += nt) coff[v] = a.var_copy_off[pi.coff_begin + v];
     for (int v = tid; v < V; v += nt) {
         const int g = a.var_gid[pi.var_begin + v];
-        crho[v] = T(a.c[g] / a.rho);
+        cvar[v] = T(a.c[g]);
         vlo[v] = T(a.lo[g]);
         vhi[v] = T(a.hi[g]);
         vcnt[v] = T(1.0 / a.cnt[g]);  // reciprocal of the copy count N_i
@@ -390,13 +416,52 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         }
         return s;
     };
+    // Aggregated residual form: a boundary variable's per-owner sums of
+    // rho (x_k - x_k_prev) and of lambda_k over its copies go to its first
+    // owner (owner index 0), which adds the m sums in owner order, squares
+    // the two totals and empties the words. Words: [parity][quantity][slot],
+    // the slot of (reader 0, writer me) = slot base + me.
+    auto agg_publish = [&](int par, int v, double dsum, double lsum) {
+        double* w0 = a.bagg + int64_t(par) * 2 * ns + sbase[v] + sme[v];
+        st_agent(w0, dsum);
+        st_agent(w0 + ns, lsum);
+    };
+    auto agg_collect = [&](int par, int v, double* d2, double* l2) {
+        double* w0 = a.bagg + int64_t(par) * 2 * ns + sbase[v];
+        const int m = sm_[v];
+        double ds = 0.0, ls = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double dj = await_word(w0 + j, ld_word(w0 + j), limit, &ok_lds);
+            const double lj = await_word(w0 + ns + j, ld_word(w0 + ns + j), limit, &ok_lds);
+            st_empty(w0 + j);
+            st_empty(w0 + ns + j);
+            ds = j == 0 ? dj : ds + dj;
+            ls = j == 0 ? lj : ls + lj;
+        }
+        *d2 += ds * ds;
+        *l2 += ls * ls;
+    };
+    // one wave's aggregated sums into LDS for the test wave (every lane active)
+    auto agg_to_lds = [&](double d2, double l2) {
+        d2 = group_sum(d2, 16);
+        l2 = group_sum(l2, 16);
+        d2 = read_lane(d2, 0) + read_lane(d2, 16) + read_lane(d2, 32) + read_lane(d2, 48);
+        l2 = read_lane(l2, 0) + read_lane(l2, 16) + read_lane(l2, 32) + read_lane(l2, 48);
+        if (lane == 0) {
+            aggw[wv * 2] = d2;
+            aggw[wv * 2 + 1] = l2;
+        }
+    };
+    // interior variables' aggregated sums of the last published sweep, carried
+    // by the thread that owns them from the publication to the next global update
+    double agg_d2 = 0.0, agg_l2 = 0.0;
 
     // ---- partial sums of the starting state for the first global update
     for (int v = tid; tid < g_threads && v < V; v += g_threads) {
         T acc = T(0);
         for (int q = coff[v]; q < coff[v + 1]; ++q) {
             const int r = crow[q];
-            acc += XS(0)[r] - LAM(0)[r] * irho;
+            acc += XS(0)[r] - LAM(0)[r] * irho_c;
         }
         ownp[v] = acc;
         publish(a.bpart, v, acc);
@@ -417,36 +482,39 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     static_assert(kGroup == 16, "one lane row per group");
     const bool leader = blockIdx.x % kGroup == 0;
     const unsigned grp = blockIdx.x / kGroup, ngroups = (P + kGroup - 1) / kGroup;
-    const int qa = lane >> 4, gi = lane & 15;
+    // word B holds quantity 4 (lanes < 16) and, in the aggregated form, the
+    // aggregated dual residual and dual norm (quantities 5, 6; lanes 16..47)
+    constexpr int nqb = AGG ? 3 : 1, nq = 4 + nqb;
+    const int qa = lane >> 4, gi = lane & 15, qb = 4 + qa;
     const unsigned member = blockIdx.x + unsigned(gi);
-    const bool mem_a = member < P, mem_b = mem_a && lane < 16;
-    const bool grp_a = unsigned(gi) < ngroups, grp_b = grp_a && lane < 16;
+    const bool mem_a = member < P, mem_b = mem_a && qa < nqb;
+    const bool grp_a = unsigned(gi) < ngroups, grp_b = grp_a && qa < nqb;
     unsigned long long w1a = 0, w1b = 0, w2a = 0, w2b = 0;
     auto ring1 = [&](int64_t sweep) -> double* { return a.rpart + int64_t(sweep & (kRing - 1)) * P * 8; };
     auto ring2 = [&](int64_t sweep) -> double* { return a.gpart + int64_t(sweep & (kRing - 1)) * 8 * kGroup; };
     auto issue_members = [&](int64_t sweep) {
         const double* base = ring1(sweep) + member;
         w1a = mem_a ? ld_word(base + qa * P) : 0ull;
-        w1b = mem_b ? ld_word(base + 4 * P) : 0ull;
+        w1b = mem_b ? ld_word(base + qb * P) : 0ull;
     };
     auto issue_groups = [&](int64_t sweep) {
         const double* base = ring2(sweep) + gi;
         w2a = grp_a ? ld_word(base + qa * kGroup) : 0ull;
-        w2b = grp_b ? ld_word(base + 4 * kGroup) : 0ull;
+        w2b = grp_b ? ld_word(base + qb * kGroup) : 0ull;
     };
     // leader: its members' sums of `sweep` added and published; the members'
     // words emptied (the leader is their only reader)
     auto group_sums = [&](int64_t sweep) {
         double* base = ring1(sweep) + member;
         double va = mem_a ? await_word(base + qa * P, w1a, limit, &ok_lds) : 0.0;
-        double vb = mem_b ? await_word(base + 4 * P, w1b, limit, &ok_lds) : 0.0;
+        double vb = mem_b ? await_word(base + qb * P, w1b, limit, &ok_lds) : 0.0;
         va = group_sum(va, kGroup);
         vb = group_sum(vb, kGroup);
         double* g = ring2(sweep) + grp;
         if (gi == 0) st_agent(g + qa * kGroup, va);
-        if (lane == 0) st_agent(g + 4 * kGroup, vb);
+        if (gi == 0 && qa < nqb) st_agent(g + qb * kGroup, vb);
         if (mem_a) st_empty(base + qa * P);
-        if (mem_b) st_empty(base + 4 * P);
+        if (mem_b) st_empty(base + qb * P);
     };
     uint64_t tprof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint64_t tw_prof = 0;  // wave tw's time in the test's totals, inside phase 0
@@ -464,33 +532,60 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     int64_t result = 0;   // sweep whose state is returned
     int converged = 0, nonfinite = 0;
     bool ok = true;
-    double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double d[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double sq = sqrt(double(a.nloc));
+    // dimension of the dual residual's vector: every copy, or (aggregated
+    // form) every global variable
+    const double sqd = AGG ? sqrt(double(a.n)) : sq;
+    // residual balancing, kept by lane 0 of wave tw: rho of the latest sweep
+    // scheduled so far, and the changes decided
+    double rho_sched = a.rho;
+    int64_t rho_changes = 0;
     // termination test of one finished sweep; identical on every workgroup
     // wave tw: the grid-wide sums of one sweep from the group sums (loads
-    // issued by issue_groups), into LDS for every thread
-    auto totals = [&](int64_t sweep) {
+    // issued by issue_groups), into LDS for every thread. With may_change,
+    // also the residual-balancing rule for that sweep (same sums, hence the
+    // same decision on every workgroup).
+    auto totals = [&](int64_t sweep, bool may_change) {
         const double* base = ring2(sweep) + gi;
         double va = grp_a ? await_word(base + qa * kGroup, w2a, limit, &ok_lds) : 0.0;
-        double vb = grp_b ? await_word(base + 4 * kGroup, w2b, limit, &ok_lds) : 0.0;
+        double vb = grp_b ? await_word(base + qb * kGroup, w2b, limit, &ok_lds) : 0.0;
         va = group_sum(va, kGroup);
         vb = group_sum(vb, kGroup);
-        // the grid totals: quantity q < 4 in lane 16q of A, quantity 4 in
-        // lane 0 of B; their square roots taken lane-parallel
+        // the grid totals: quantity q < 4 in lane 16q of A, quantity 4 + q
+        // in lane 16q of B; their square roots taken lane-parallel
         if (gi == 0) tot[qa] = va;
-        if (lane == 0) tot[4] = vb;
+        if (gi == 0 && qa < nqb) tot[qb] = vb;
         const double ra = sqrt(va), rb = sqrt(vb);
         const double r0 = read_lane(ra, 0), r1 = read_lane(ra, 16), r2 = read_lane(ra, 32), r3 = read_lane(ra, 48);
         const double r4 = read_lane(rb, 0);
+        const double r5 = AGG ? read_lane(rb, 16) : 0.0, r6 = AGG ? read_lane(rb, 32) : 0.0;
         // the test itself, once per workgroup (lane 0 of wave tw); the sums
-        // are of squares, so a non-finite sum shows in its square root
+        // are of squares, so a non-finite sum shows in its square root (the
+        // dual residual sums are of rho (x_s - x_s_prev), rho of that sweep)
         if (lane == 0) {
-            const double pres = r0, dres = a.rho * r1;
+            const double pres = r0, dres = AGG ? r5 : r1;
             const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(r2, r3);
-            const double eps_d = sq * a.eps_abs + a.eps_rel * r4;
-            const int nf = !isfinite(r0 + r1 + r2 + r3 + r4);
+            const double eps_d = sqd * a.eps_abs + a.eps_rel * (AGG ? r6 : r4);
+            const int nf = !isfinite(r0 + r1 + r2 + r3 + r4 + r5 + r6);
             const int cv = pres <= eps_p && dres <= eps_d;
-            test_lds = ((nf || (a.check && cv)) ? 1 : 0) | (cv ? 2 : 0) | (nf ? 4 : 0);
+            const int stop = nf || (a.check && cv);
+            test_lds = (stop ? 1 : 0) | (cv ? 2 : 0) | (nf ? 4 : 0);
+            const int period = rule_period;
+            if (may_change && !stop && period > 0 && sweep % period == 0 && rho_changes < rule_max && eps_p > 0.0 &&
+                eps_d > 0.0) {
+                const double rr = pres / eps_p, ss = dres / eps_d, mu = rule_mu, tau = rule_tau;
+                const double f = rr > mu * ss ? tau : (ss > mu * rr ? 1.0 / tau : 1.0);
+                if (f != 1.0) {
+                    rho_sched *= f;
+                    if (blockIdx.x == 0) {
+                        double* lg = rule_log;
+                        lg[2 * rho_changes] = double(sweep + kRhoLag);
+                        lg[2 * rho_changes + 1] = rho_sched;
+                    }
+                    ++rho_changes;
+                }
+            }
             if (blockIdx.x == 0 && sweep <= a.hist_cap && ok_lds) {
                 double* h = a.hist + (sweep - 1) * 4;
                 h[0] = pres;
@@ -519,13 +614,16 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             // the test of sweep done - 2, during the global update
             if (done >= 3) {
                 const uint64_t t0 = PROF ? wall_clock64() : 0;
-                totals(done - 2);
+                totals(done - 2, true);
                 if (PROF && lane == 0) tw_prof += wall_clock64() - t0;
                 // every part has read the group sums of sweep done - 5: their
                 // sums of sweep done - 2 are all in, and each part tests
                 // sweep j before it publishes sweep j + 3
-                if (leader && lane < 5 && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
+                if (leader && lane < nq && done >= 6) st_empty(ring2(done - 5) + lane * kGroup + grp);
             }
+            // rho of sweep done + 2 (a change decided from the test of sweep
+            // done - 2), read by the row waves after B1
+            if (lane == 0) rho_of[(done + 2) & 7] = rho_sched;
             __syncthreads();  // B1
             if (ok_lds == 0) {
                 ok = false;
@@ -535,6 +633,15 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                 result = done - 2;
                 stopped = true;
                 break;
+            }
+            if (AGG && done >= 1) {
+                // this part's aggregated sums of sweep done (completed by the
+                // row waves' global update) beside its other sums of that sweep
+                if (lane < 2) {
+                    double q = 0.0;
+                    for (int w = 0; w < n_work; ++w) q += aggw[w * 2 + lane];
+                    st_agent(ring1(done) + (5 + lane) * P + blockIdx.x, q);
+                }
             }
             __syncthreads();  // B2
             // its stores of the last phase complete first (issued a phase or
@@ -556,7 +663,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             if (done >= 2) {
                 const double* base = ring2(done - 1) + gi;
                 if (grp_a && w2a == Word<double>::kEmpty) w2a = ld_word(base + qa * kGroup);
-                if (grp_b && w2b == Word<double>::kEmpty) w2b = ld_word(base + 4 * kGroup);
+                if (grp_b && w2b == Word<double>::kEmpty) w2b = ld_word(base + qb * kGroup);
             }
             // this part's sums of the sweep from the row sums of the work
             // waves: lane 8q + j adds rows j, j + 8, ... of quantity q, then
@@ -579,14 +686,19 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             T* bcur = a.bpart + int64_t(bp) * ns;
             T* bnx = a.bpart + int64_t(bp ^ 1) * ns;
             T* xg = XL(int((done + 1) & 3));
-            // closed_1: clipped average of the copies
+            // closed_1: clipped average of the copies; in the aggregated
+            // form, owner 0 of each boundary variable also completes the
+            // aggregated sums of sweep done
+            double ad2 = agg_d2, al2 = agg_l2;
             for (int v = tid; v < V; v += g_threads) {
                 const T s = sbase[v] < 0 ? ownp[v] : gather(bcur, v);
-                T xv = (s - crho[v]) * vcnt[v];
+                if (AGG && done >= 1 && sbase[v] >= 0 && sme[v] == 0) agg_collect(bp, v, &ad2, &al2);
+                T xv = (s - cvar[v] * irho_c) * vcnt[v];
                 xv = xv < vlo[v] ? vlo[v] : xv;
                 xv = xv > vhi[v] ? vhi[v] : xv;
                 xg[v] = xv;
             }
+            if (AGG && done >= 1) agg_to_lds(ad2, al2);
             if (PROF && tid == 0) tprof[7] += wall_clock64() - tlast;  // the workgroup's own global update, inside phase 0
             __syncthreads();  // B1
             if (ok_lds == 0) {
@@ -600,10 +712,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                 stopped = true;
                 break;
             }
+            // rho of the next sweep, whose global update this sweep's
+            // published partial sums feed
+            const double rho_n = in_vgpr(rho_of[(done + 2) & 7]);
+            irho_n = in_vgpr(T(1.0 / rho_n));
             stamp(0);
             // v = B_s x + lambda_s / rho
             const T* lc = LAM(cur);
-            for (int r = tid; r < R; r += g_threads) vb[r] = xg[rlv[r]] + lc[r] * irho;
+            for (int r = tid; r < R; r += g_threads) vb[r] = xg[rlv[r]] + lc[r] * irho_c;
             __syncthreads();  // B2
             stamp(1);
             // t = W v: GA lanes per (subsystem, basis row) task, then a lane-group sum
@@ -663,11 +779,11 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                     const T vr = vb[r];
                     const T y = mode1 ? bbar[r] + (vr - acc) : bbar[r] + acc;
                     const T z = xg[rlv[r]];
-                    const T lnew = lc[r] + rho * (z - y);
+                    const T lnew = lc[r] + rho_cT * (z - y);
                     xn[r] = y;
                     ln[r] = lnew;
                     const double dz = double(z) - double(y);
-                    const double dx = double(y) - double(xc[r]);
+                    const double dx = rho_c * (double(y) - double(xc[r]));
                     p0 += dz * dz;
                     p1 += dx * dx;
                     p2 += double(z) * double(z);
@@ -692,16 +808,39 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             // partial sums for the next global update; publish boundary slots
             // (every variable has a copy in the part; its first copy's row
             // is read beside the copy range)
+            agg_d2 = 0.0;
+            agg_l2 = 0.0;
             for (int v = tid; v < V; v += g_threads) {
                 const int r0 = vr0[v], c0 = coff[v], c1 = coff[v + 1];
-                T acc = T(0) + (xn[r0] - ln[r0] * irho);
+                T acc = T(0) + (xn[r0] - ln[r0] * irho_n);
+                double dsum = 0.0, lsum = 0.0;
+                if (AGG) {
+                    dsum = double(xn[r0]) - double(xc[r0]);
+                    lsum = double(ln[r0]);
+                }
                 for (int q = c0 + 1; q < c1; ++q) {
                     const int r = crow[q];
-                    acc += xn[r] - ln[r] * irho;
+                    acc += xn[r] - ln[r] * irho_n;
+                    if (AGG) {
+                        dsum += double(xn[r]) - double(xc[r]);
+                        lsum += double(ln[r]);
+                    }
                 }
                 ownp[v] = acc;
                 publish(bnx, v, acc);
+                if (AGG) {
+                    dsum *= rho_c;
+                    if (sbase[v] < 0) {
+                        agg_d2 += dsum * dsum;
+                        agg_l2 += lsum * lsum;
+                    } else {
+                        agg_publish(bp ^ 1, v, dsum, lsum);
+                    }
+                }
             }
+            rho_c = rho_n;
+            rho_cT = in_vgpr(T(rho_n));
+            irho_c = irho_n;
             stamp(4);
             ++done;
             cur = nx;
@@ -712,6 +851,23 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         // max_iter reached: the group sums of the last sweep, then the
         // sweeps not yet tested, in order
         result = done;
+        if (AGG && done >= 1) {
+            // the aggregated sums of the last sweep, which no further global
+            // update completes
+            if (wv != tw) {
+                double ad2 = agg_d2, al2 = agg_l2;
+                const int bp = int(done & 1);
+                for (int v = tid; v < V; v += g_threads)
+                    if (sbase[v] >= 0 && sme[v] == 0) agg_collect(bp, v, &ad2, &al2);
+                agg_to_lds(ad2, al2);
+            }
+            __syncthreads();
+            if (wv == tw && lane < 2) {
+                double q = 0.0;
+                for (int w = 0; w < n_work; ++w) q += aggw[w * 2 + lane];
+                st_agent(ring1(done) + (5 + lane) * P + blockIdx.x, q);
+            }
+        }
         if (wv == tw && leader && done >= 1) {
             __builtin_amdgcn_s_waitcnt(0);
             issue_members(done);
@@ -720,7 +876,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         for (int64_t k = done > 3 ? done - 2 : 1; k <= done; ++k) {
             if (wv == tw) {
                 issue_groups(k);
-                totals(k);
+                totals(k, false);
             }
             __syncthreads();
             result = k;
@@ -741,14 +897,24 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     if (tid == 0 && (!ok || nonfinite)) atomicOr(&a.st->flags, (ok ? 0 : 1) | (nonfinite ? 2 : 0));
     if (blockIdx.x == 0 && tid == 0) {
         if (result > 0)
-            for (int q = 0; q < 5; ++q) d[q] = tot[q];
+            for (int q = 0; q < nq; ++q) d[q] = tot[q];
         a.st->iters = result;
         a.st->computed = done;
         a.st->converged = converged;
         a.st->pres = sqrt(d[0]);
-        a.st->dres = a.rho * sqrt(d[1]);
+        a.st->dres = sqrt(AGG ? d[5] : d[1]);
         a.st->eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
-        a.st->eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
+        a.st->eps_d = sqd * a.eps_abs + a.eps_rel * sqrt(AGG ? d[6] : d[4]);
+        a.st->rho = result > 0 ? rho_of[result & 7] : a.rho;
+    }
+    if (blockIdx.x == 0 && wv == tw && lane == 0) {
+        // the changes whose first sweep was reached (a change decided near
+        // the end may fall after the returned sweep)
+        int64_t nch = 0;
+        const double* lg = rule_log;
+        for (int64_t i = 0; i < rho_changes; ++i)
+            if (int64_t(lg[2 * i]) <= result) ++nch;
+        a.st->rho_changes = nch;
     }
     if (PROF && a.prof && tid == 0)
         for (int i = 0; i < 8; ++i)
@@ -760,19 +926,22 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
 // the status cleared (plain stores).
 template <typename T>
 __global__ void reset_sync_kernel(T* bpart, int64_t n_bwords, double* rpart, int64_t n_rwords, double* gpart,
-                                  int64_t n_gwords, SweepStatus* st) {
+                                  int64_t n_gwords, double* bagg, int64_t n_awords, SweepStatus* st) {
     const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x, stride = int64_t(gridDim.x) * blockDim.x;
     using UB = typename Word<T>::U;
     using UR = typename Word<double>::U;
     for (int64_t i = i0; i < n_bwords; i += stride) reinterpret_cast<UB*>(bpart)[i] = Word<T>::kEmpty;
     for (int64_t i = i0; i < n_rwords; i += stride) reinterpret_cast<UR*>(rpart)[i] = Word<double>::kEmpty;
     for (int64_t i = i0; i < n_gwords; i += stride) reinterpret_cast<UR*>(gpart)[i] = Word<double>::kEmpty;
+    for (int64_t i = i0; i < n_awords; i += stride) reinterpret_cast<UR*>(bagg)[i] = Word<double>::kEmpty;
     if (i0 == 0) {
         st->iters = 0;
         st->computed = 0;
         st->converged = 0;
         st->flags = 0;
         st->pres = st->dres = st->eps_p = st->eps_d = 0.0;
+        st->rho = 0.0;
+        st->rho_changes = 0;
     }
 }
 
@@ -785,14 +954,20 @@ hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <typename T, bool PROF>
+template <typename T, bool PROF, bool AGG>
 static const void* sweep_ptr() {
-    return reinterpret_cast<const void*>(&sweep_kernel<T, PROF>);
+    return reinterpret_cast<const void*>(&sweep_kernel<T, PROF, AGG>);
+}
+
+template <typename T>
+static const void* sweep_variant(bool prof, bool agg) {
+    if (agg) return prof ? sweep_ptr<T, true, true>() : sweep_ptr<T, false, true>();
+    return prof ? sweep_ptr<T, true, false>() : sweep_ptr<T, false, false>();
 }
 
 hipError_t prepare_sweep(bool fp32, size_t lds_bytes) {
-    for (const void* f : {fp32 ? sweep_ptr<float, false>() : sweep_ptr<double, false>(),
-                          fp32 ? sweep_ptr<float, true>() : sweep_ptr<double, true>()}) {
+    for (int v = 0; v < 4; ++v) {
+        const void* f = fp32 ? sweep_variant<float>(v & 1, v & 2) : sweep_variant<double>(v & 1, v & 2);
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
         if (e != hipSuccess) return e;
     }
@@ -800,22 +975,32 @@ hipError_t prepare_sweep(bool fp32, size_t lds_bytes) {
 }
 
 hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu) {
-    const void* f = fp32 ? sweep_ptr<float, false>() : sweep_ptr<double, false>();
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
+    // the fewest co-resident workgroups of any variant the handle may launch
+    int best = 1 << 30;
+    for (int v = 0; v < 4; ++v) {
+        const void* f = fp32 ? sweep_variant<float>(v & 1, v & 2) : sweep_variant<double>(v & 1, v & 2);
+        int n = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds_bytes);
+        if (e != hipSuccess) return e;
+        best = std::min(best, n);
+    }
+    *blocks_per_cu = best;
+    return hipSuccess;
 }
 
 template <typename T>
 static hipError_t launch_sweep_t(const SweepArgs<T>& a, int grid, int block, size_t lds, hipStream_t stream) {
     const int64_t nb = 2 * std::max<int64_t>(a.n_slots, 1), nr = int64_t(kRing) * a.P * 8;
     const int64_t ng = int64_t(kRing) * 8 * kGroup;
-    const unsigned rgrid = unsigned(std::min<int64_t>(256, (std::max(nb, nr) + 255) / 256));
+    const int64_t na = a.bagg ? 4 * std::max<int64_t>(a.n_slots, 1) : 0;
+    const unsigned rgrid = unsigned(std::min<int64_t>(256, (std::max(std::max(nb, nr), na) + 255) / 256));
     hipLaunchKernelGGL(reset_sync_kernel<T>, dim3(rgrid), dim3(256), 0, stream, a.bpart, nb, a.rpart, nr, a.gpart, ng,
-                       a.st);
+                       a.bagg, na, a.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     SweepArgs<T> copy = a;
     void* args[] = {&copy};
-    const void* f = a.prof ? sweep_ptr<T, true>() : sweep_ptr<T, false>();
+    const void* f = sweep_variant<T>(a.prof != nullptr, a.bagg != nullptr);
     return hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), args, unsigned(lds), stream);
 }
 

@@ -73,5 +73,7 @@ inline void need(const void* p, const char* what) {
 
 // Option checks shared by the plain and the batched solver.
 void check_options(const ldopf_options& o);
+// What the batched form adds: the literal residual form and a fixed rho.
+void check_batch_options(const ldopf_options& o);
 
 }  // namespace ldopf

@@ -20,6 +20,7 @@ struct LdsLayout {
     uint32_t tk_m, row_m;  // uint2 per task / per row: operator offsets packed at load time
     uint32_t var_r0;       // u16 per var: the row of its first copy
     uint32_t red;                                                                // double [waves][4][8], then [8]
+    uint32_t agg;          // double [waves][2]: the aggregated residual sums of each row wave
     uint32_t total;
 };
 
@@ -63,6 +64,7 @@ LDOPF_HD inline LdsLayout lds_layout(uint32_t w, uint32_t w_words, uint32_t rows
     L.row_m = take(8 * rows);
     L.var_r0 = take(2 * vars);
     L.red = take(8 * 8 * (4 * waves + 1));  // row sums of each wave's 4 rows, then the grid totals
+    L.agg = take(8 * 2 * waves);
     L.total = o;
     return L;
 }

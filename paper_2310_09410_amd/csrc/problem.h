@@ -38,6 +38,8 @@ struct ldopf_problem {
     uint64_t spin_limit = 0;
 
     DevBuf<double> A, b, basis, abar, bbar, c, lo, hi, cnt, xs, lam, x, hist, rpart, gpart, prof;
+    DevBuf<double> rholog;  // [kMaxRhoChanges][2] residual-balancing changes of the last solve
+    DevBuf<double> bagg;    // aggregated residual form: boundary words (allocated at the first such solve)
     std::vector<double> phase_ms;  // [parts][8] per-phase ms of the last profiled solve
     double tick_ms = 1e-5;  // wall-clock tick in ms
     DevBuf<int32_t> ns, ms, rank_d, flags;
@@ -70,6 +72,7 @@ struct SyncWords {
     void* bpart;
     double* rpart;
     double* gpart;
+    double* bagg;  // null unless the aggregated residual form is selected
     SweepStatus* st;
 };
 // Device bytes of the synchronisation words of the handle's sweep.

@@ -13,7 +13,8 @@ import numpy as np
 from . import _native as N
 from ._native import (LDOPF_FP32_MIXED, LDOPF_FP64, LDOPF_NOT_CONVERGED, LDOPF_OK,  # noqa: F401
                       LDOPF_REQ_DONE, LDOPF_REQ_FAILED, LDOPF_REQ_QUEUED, LDOPF_REQ_RUNNING,
-                      LDOPF_RESIDUAL_AGGREGATED, LDOPF_RESIDUAL_PAPER, ldopf_batch_sizes, ldopf_batch_status,
+                      LDOPF_RESIDUAL_AGGREGATED, LDOPF_RESIDUAL_PAPER, LDOPF_RHO_BALANCE, LDOPF_RHO_FIXED,
+                      ldopf_batch_sizes, ldopf_batch_status,
                       ldopf_options, ldopf_server_stats, ldopf_sizes, ldopf_status)
 
 
@@ -183,6 +184,16 @@ class Problem:
         _check(N.lib().ldopf_get_operators(self.h, _ptr(ab, C.c_double), ab.shape[0], _ptr(bb, C.c_double),
                                            bb.shape[0], _ptr(rk, C.c_int32), rk.shape[0]), "ldopf_get_operators")
         return ab, bb, rk
+
+    def get_rho_log(self):
+        """[(first sweep, rho)] of every change residual balancing made in the last solve."""
+        ln = C.c_int64(0)
+        _check(N.lib().ldopf_get_rho_log(self.h, None, None, 0, C.byref(ln)), "ldopf_get_rho_log")
+        sw = np.empty(ln.value, np.int64)
+        rh = np.empty(ln.value)
+        _check(N.lib().ldopf_get_rho_log(self.h, _ptr(sw, C.c_int64), _ptr(rh, C.c_double), ln.value, C.byref(ln)),
+               "ldopf_get_rho_log")
+        return [(int(a), float(b)) for a, b in zip(sw, rh)]
 
     def get_phase_times(self, part: int = 0) -> np.ndarray:
         """Per-phase ms of workgroup `part` in the last profiled solve."""

@@ -118,6 +118,10 @@ def test_fp32_mixed_fixed_sweeps(gpu):
 
 @pytest.mark.parametrize("name", ["13", "123"])
 def test_fp32_mixed_converged(gpu, name):
+    """The precision claim of Section V-B (Table 5: the FP32 GPU run takes
+    the FP64 CPU run's iteration count): the FP32-mixed stopping sweep within
+    2% of the FP64 oracle's, and x and the objective within 1e-4 of the
+    converged oracle's."""
     from oracle import admm
     P = gpu
     prob = P.ldopf_create(feeder(name), _opts(P, precision=P.ldopf.LDOPF_FP32_MIXED))
@@ -125,11 +129,9 @@ def test_fp32_mixed_converged(gpu, name):
     ref = admm.solve(oracle_prep(name))
     assert st.converged
     assert st.pres <= st.eps_prim and st.dres <= st.eps_dual
-    # FP32 stopping sweep: see the note in test_gpu_batch.py
-    assert abs(st.iterations - ref.iters) <= 0.25 * ref.iters
-    same = admm.solve(oracle_prep(name), max_iter=st.iterations, check=False)
-    assert rel_err(prob.get_global(), same.x) <= 1e-4
-    assert abs(prob.objective() - same.objective) / max(1.0, abs(same.objective)) <= 1e-4
+    assert abs(st.iterations - ref.iters) <= 0.02 * ref.iters, (st.iterations, ref.iters)
+    assert rel_err(prob.get_global(), ref.x) <= 1e-4
+    assert abs(prob.objective() - ref.objective) / max(1.0, abs(ref.objective)) <= 1e-4
 
 
 def test_bitwise_repeatable_and_warm_start(gpu):

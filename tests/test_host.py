@@ -137,3 +137,57 @@ def test_options_out_of_range_are_rejected_before_any_device_work(field, value):
     with pytest.raises(LdopfError) as e:
         P.ldopf_create(dict(feeder("13")), o)
     assert e.value.code == -1
+
+
+def test_create_lp_validation_before_any_device_work():
+    """ldopf_create_lp checks the B_s invariants of Section III-A (strictly
+    ascending, hence distinct, global indices in a subsystem; every global
+    variable with at least one copy, since closed_1 divides by N_i) and the
+    bounds on the host, before touching the device."""
+    import paper_2310_09410_amd as P
+    n_s = np.array([2, 2], np.int32)
+    m_s = np.array([1, 0], np.int32)
+    A = np.array([1.0, 1.0])
+    b = np.array([1.0])
+    c, lo, hi = np.zeros(3), np.full(3, -1.0), np.ones(3)
+
+    def code(**kw):
+        args = dict(n=3, c=c, lo=lo, hi=hi, x_init=None, n_s=n_s, m_s=m_s, A=A, b=b,
+                    gidx=np.array([0, 1, 1, 2], np.int64))
+        args.update(kw)
+        with pytest.raises(P.LdopfError) as e:
+            P.ldopf_create_lp(args["n"], args["c"], args["lo"], args["hi"], args["x_init"], args["n_s"], args["m_s"],
+                              args["A"], args["b"], args["gidx"])
+        return e.value.code
+
+    assert code(gidx=np.array([0, 0, 1, 2], np.int64)) == -1      # duplicate index inside a subsystem
+    assert code(gidx=np.array([1, 0, 1, 2], np.int64)) == -1      # not ascending
+    assert code(n=4, c=np.zeros(4), lo=np.full(4, -1.0), hi=np.ones(4)) == -1  # variable 3 has no copy (N_i = 0)
+    assert code(gidx=np.array([0, 1, 1, 3], np.int64)) == -1      # index out of range
+    assert code(lo=np.array([-1.0, 2.0, -1.0])) == -3             # lo > hi
+    assert code(b=np.array([np.nan])) == -1                       # non-finite data
+    assert code(x_init=np.array([0.0, np.inf, 0.0])) == -1
+
+
+@pytest.mark.parametrize("field,value", [
+    ("rho_update", 2), ("rho_period", 3), ("rho_max_changes", 1025), ("rho_mu", 1.0), ("rho_tau", 0.5),
+    ("residual_form", 2),
+])
+def test_rho_and_residual_options_are_checked(field, value):
+    import paper_2310_09410_amd as P
+    o = P.ldopf_default_options(rho_update=1)
+    setattr(o, field, value)
+    with pytest.raises(P.LdopfError) as e:
+        P.ldopf_create(dict(feeder("13")), o)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("field", ["residual_form", "rho_update"])
+def test_batch_refuses_what_it_does_not_run(field):
+    import paper_2310_09410_amd as P
+    net = feeder("13")
+    o = P.ldopf_default_options(precision=1)
+    setattr(o, field, 1)
+    with pytest.raises(P.LdopfError) as e:
+        P.ldopf_batch_create(net, np.ones((2, int(net["n_load"]))), o)
+    assert e.value.code == -9
