@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libldopf.so")
+# LDOPF_LIBRARY selects another build of the same library (the host
+# sanitizer build of build.build_sanitized); default: the in-tree build.
+LIB_PATH = os.environ.get("LDOPF_LIBRARY") or os.path.join(HERE, "libldopf.so")
 
 LDOPF_OK = 0
 LDOPF_NOT_CONVERGED = 1

@@ -60,5 +60,42 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host-side checks: the host sources with AddressSanitizer and
+# UndefinedBehaviorSanitizer (g++), linked with the device objects of the last
+# build(). Nothing on the GPU is instrumented; the library serves host-only
+# calls (assembly, validation, planning) run under LD_PRELOAD of libasan.
+SAN_LIB = os.path.join(HERE, "_build", "libldopf_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g", "-O1"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    objdir = os.path.join(HERE, "_build")
+    dev_objs = [os.path.join(objdir, s + ".o") for s in SOURCES if s.endswith(".hip")]
+    missing = [o for o in dev_objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"device objects missing ({missing}): run build() first")
+    gxx = shutil.which("g++") or "g++"
+    host_flags = [f for f in CXX_FLAGS if f != "-O3"] + SAN_FLAGS
+    objs = []
+    for src in SOURCES:
+        if src.endswith(".hip"):
+            continue
+        obj = os.path.join(objdir, src + ".san.o")
+        cmd = [gxx, *host_flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    cmd = [gxx, "-shared", "-o", SAN_LIB, *objs, *dev_objs, "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,/opt/rocm/lib", *SAN_FLAGS]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -191,3 +191,12 @@ def test_batch_refuses_what_it_does_not_run(field):
     with pytest.raises(P.LdopfError) as e:
         P.ldopf_batch_create(net, np.ones((2, int(net["n_load"]))), o)
     assert e.value.code == -9
+
+
+@pytest.mark.parametrize("name", ["13", "123", "2500", "8500"])
+def test_request_estimate_plans_on_the_host(name):
+    """The serving admission's estimate assembles, decomposes and plans the
+    sweep's workgroups on the host (full row rank assumed), with no GPU."""
+    import paper_2310_09410_amd as P
+    b, w = P.ldopf_request_estimate(feeder(name))
+    assert b > 0 and 1 <= w <= 256
