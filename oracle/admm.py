@@ -245,18 +245,67 @@ class Result:
     rho_log: list = dataclasses.field(default_factory=list)  # (first sweep, rho) of every change
 
 
+class Float32Steps:
+    """The global, local and dual updates with every operand and result in
+    float32 (the FP32-mixed form: operators precomputed in FP64 and rounded
+    to float32, the state in float32; the residual norms and the test stay
+    FP64). Sums over copies accumulate in float32 in copy order."""
+
+    def __init__(self, prep: Prepared):
+        lp = prep.lp
+        self.prep = prep
+        self.Abar = prep.Abar_blk.astype(np.float32)
+        self.bbar = prep.bbar.astype(np.float32)
+        self.N = prep.N.astype(np.float32)
+        self.c = lp.c.astype(np.float32)
+        self.lo = lp.lo.astype(np.float32)
+        self.hi = lp.hi.astype(np.float32)
+
+    def global_update(self, xs, lam, rho):
+        n = self.prep.lp.n
+        sx = np.zeros(n, np.float32)
+        sl = np.zeros(n, np.float32)
+        np.add.at(sx, self.prep.gidx, xs)
+        np.add.at(sl, self.prep.gidx, lam)
+        r = np.float32(rho)
+        return np.minimum(np.maximum((sx - (self.c + sl) / r) / self.N, self.lo), self.hi)
+
+    def local_update(self, x, lam, rho):
+        r = np.float32(rho)
+        z = x[self.prep.gidx]
+        d = -r * z - lam
+        return z, (self.Abar @ d) / r + self.bbar
+
+    @staticmethod
+    def dual_update(lam, z, xs, rho):
+        return lam + np.float32(rho) * (z - xs)
+
+
 def solve(lp_or_prep, rho: float = 100.0, eps_rel: float = 1e-4, eps_abs: float = 0.0,
           max_iter: int = 1_000_000, check: bool = True, form: str = "paper",
-          state: State | None = None, on_iter=None, balance: RhoBalance | None = None) -> Result:
+          state: State | None = None, on_iter=None, balance: RhoBalance | None = None,
+          precision: str = "fp64") -> Result:
     """Run Algorithm 1 until the termination test holds (or ``max_iter`` sweeps).
 
     ``check=False`` runs exactly ``max_iter`` sweeps. ``on_iter(t, prep, state)``
     is called after every sweep (tests use it to check invariants).
     ``balance``: residual balancing of rho (RhoBalance); None keeps rho fixed.
+    ``precision="fp32"``: the three updates in float32 (Float32Steps); the
+    residuals and the test in FP64.
     """
     prep = lp_or_prep if isinstance(lp_or_prep, Prepared) else prepare(lp_or_prep)
     st = state if state is not None else initial_state(prep)
     x, xs, lam = st.x, st.xs.copy(), st.lam.copy()
+    if precision == "fp32":
+        steps = Float32Steps(prep)
+        g_up, l_up, d_up = steps.global_update, steps.local_update, steps.dual_update
+        xs, lam = xs.astype(np.float32), lam.astype(np.float32)
+    elif precision == "fp64":
+        g_up = lambda xs_, lam_, r: global_update(prep, xs_, lam_, r)  # noqa: E731
+        l_up = lambda x_, lam_, r: local_update(prep, x_, lam_, r)  # noqa: E731
+        d_up = dual_update
+    else:
+        raise ValueError(precision)
     hist = []
     converged = False
     scheduled = {}  # sweep -> rho from that sweep on
@@ -269,10 +318,14 @@ def solve(lp_or_prep, rho: float = 100.0, eps_rel: float = 1e-4, eps_abs: float 
             lam = rescale_dual(lam, rho, rho_new)
             rho = rho_new
             rho_log.append((t, rho))
-        x = global_update(prep, xs, lam, rho)
-        z, xs_new = local_update(prep, x, lam, rho)
-        lam = dual_update(lam, z, xs_new, rho)
-        r = residuals(prep, z, xs_new, xs, lam, rho, eps_rel, eps_abs, form)
+        x = g_up(xs, lam, rho)
+        z, xs_new = l_up(x, lam, rho)
+        lam = d_up(lam, z, xs_new, rho)
+        if precision == "fp32":
+            r = residuals(prep, z.astype(np.float64), xs_new.astype(np.float64), xs.astype(np.float64),
+                          lam.astype(np.float64), rho, eps_rel, eps_abs, form)
+        else:
+            r = residuals(prep, z, xs_new, xs, lam, rho, eps_rel, eps_abs, form)
         xs = xs_new
         hist.append(r)
         if on_iter is not None:
@@ -285,4 +338,5 @@ def solve(lp_or_prep, rho: float = 100.0, eps_rel: float = 1e-4, eps_abs: float 
             if f != 1.0:
                 scheduled[t + balance.lag] = rho * f
     H = np.array(hist, dtype=np.float64).reshape(-1, 4)
+    x, xs, lam = (np.asarray(v, dtype=np.float64) for v in (x, xs, lam))
     return Result(x, xs, lam, H, t, converged, float(prep.lp.c @ x), prep, rho, rho_log)
