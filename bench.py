@@ -117,6 +117,35 @@ def run_batched(P, L, make_feeder, scenario_factors, stream):
     return rec
 
 
+def run_many(P, make_feeder, stream, n13: int = 64, n123: int = 16) -> dict:
+    """Several feeders in one persistent launch (ldopf_solve_many) against
+    the same solves one after another, FP64, each to eps_rel 1e-4."""
+    nets = [make_feeder("13", 54000 + i) for i in range(n13)] + [make_feeder("123", 54500 + i) for i in range(n123)]
+    hs = [P.ldopf_create(n, P.ldopf_default_options(), stream=stream) for n in nets]
+    for h in hs:  # warm: kernels loaded, history buffers allocated
+        h.solve()
+        h.reset()
+    t0 = time.perf_counter()
+    for h in hs:
+        h.solve()
+    t_seq = time.perf_counter() - t0
+    for h in hs:
+        h.reset()
+    t0 = time.perf_counter()
+    sts = P.ldopf_solve_many(hs)
+    t_many = time.perf_counter() - t0
+    out = {"workload": f"{n13} fresh 13-bus and {n123} fresh 123-bus feeders (seeds 54000+, 54500+), FP64, "
+                       "each to eps_rel 1e-4",
+           "workgroups": int(sum(h.sizes().n_parts for h in hs)),
+           "converged": int(sum(s.converged for s in sts)),
+           "one_launch_s": t_many, "one_launch_solves_per_s": len(hs) / t_many,
+           "one_by_one_s": t_seq, "one_by_one_solves_per_s": len(hs) / t_seq,
+           "speedup": t_seq / t_many, "max_iterations": int(max(s.iterations for s in sts))}
+    for h in hs:
+        h.close()
+    return out
+
+
 def _serving_requests(make_feeder, n_req: int, seed: int, id0: int):
     """n_req requests: feeder size uniform over {13, 123, 2500, 8500} buses,
     a fresh feeder seed each (id0 + i), FP32-mixed or FP64 with probability
@@ -142,8 +171,12 @@ def _serve(P, reqs, arrivals):
             while time.perf_counter() - start < arrivals[k]:
                 time.sleep(0.0005)
         ids.append(srv.submit(net, P.ldopf_default_options(precision=prec)))
-    for rid in ids:
+        if arrivals is not None and (k + 1) % 25 == 0:
+            progress(f"serving: {k + 1} of {len(reqs)} requests submitted")
+    for k, rid in enumerate(ids):
         srv.wait(rid, 1200)
+        if (k + 1) % 25 == 0:
+            progress(f"serving: {k + 1} of {len(ids)} requests done")
     st = srv.stats()
     srv.close()
     return st
@@ -289,6 +322,8 @@ def main():
     ap.add_argument("--cpu-baseline-only", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-threads", type=int, default=1, help=argparse.SUPPRESS)
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-rho-balance", action="store_true")
+    ap.add_argument("--no-many", action="store_true")
     args = ap.parse_args()
     if args.cpu_baseline_only:
         _cpu_baseline_child(args.cpu_baseline_only, args.cpu_threads)
@@ -418,6 +453,22 @@ def main():
                              "objective": p32.objective(), "objective_rel_diff_vs_fp64":
                                  abs(p32.objective() - obj) / max(1.0, abs(obj))}
         p32.close()
+    if not args.no_rho_balance:
+        # residual balancing of rho (default rule: every 100 sweeps, mu 10,
+        # tau 2, at most 16 changes) on the same feeder, capped at 500,000 sweeps
+        pr = P.ldopf_create(net, P.ldopf_default_options(rho_update=L.LDOPF_RHO_BALANCE, max_iter=500000),
+                            stream=stream)
+        srb = pr.solve()
+        rec["rho_balance"] = {"rule": "rho x/÷ 2 when pres/eps_prim and dres/eps_dual differ by more than 10x, "
+                                      "checked every 100 sweeps, effective 4 sweeps later, at most 16 changes",
+                              "iterations": srb.iterations, "converged": bool(srb.converged),
+                              "time_s": 1e-3 * srb.sweep_ms, "rho_final": srb.rho, "rho_changes": srb.rho_changes,
+                              "objective_rel_diff_vs_fixed_rho": (pr.objective() - obj) / max(1.0, abs(obj))}
+        pr.close()
+        progress(f"rho balancing: {srb.iterations} sweeps, converged {bool(srb.converged)}")
+    if not args.no_many:
+        rec["feeders_one_launch"] = run_many(P, make_feeder, stream)
+        progress(f"feeders in one launch: {rec['feeders_one_launch']['speedup']:.1f}x one by one")
     if not args.no_batched:
         rec["batched"] = run_batched(P, L, make_feeder, scenario_factors, stream)
         progress(f"batched: {rec['batched']['solves_per_s']:.2f} solves/s")

@@ -284,6 +284,24 @@ LDOPF_API int ldopf_solve(ldopf_problem* h, ldopf_status* status);
  */
 LDOPF_API int ldopf_solve_noalloc(ldopf_problem* h, ldopf_status* status);
 
+/*
+ * Several problems (different feeders, or one feeder with different data)
+ * solved together in one persistent launch: each runs Algorithm 1 on its
+ * own -- its global, local and dual updates, its exchange words, its
+ * termination test (Section III-C) and its stop -- while their workgroups
+ * share the GPU. Results equal ldopf_solve's on each problem bit for bit.
+ * problems[count]: created on one device with the same precision, residual
+ * form and profiling option, none repeated; together their workgroups must
+ * fit on the device at once (else LDOPF_UNSUPPORTED and nothing runs: solve
+ * them in smaller groups). statuses[count] (nullable) receives each
+ * problem's status as ldopf_solve reports it; status.sweep_ms is the time of
+ * the shared launch. Runs on the first problem's stream after every
+ * problem's earlier work; blocks until done. Returns LDOPF_OK when every
+ * problem did, else the most severe code among them (an error before
+ * LDOPF_NOT_CONVERGED).
+ */
+LDOPF_API int ldopf_solve_many(ldopf_problem* const* problems, int32_t count, ldopf_status* statuses);
+
 /* Back to the initial point of Section V-A. */
 LDOPF_API int ldopf_reset(ldopf_problem* h);
 

@@ -126,6 +126,7 @@ SIGNATURES = {
     "ldopf_set_options": (C.c_int, [C.c_void_p, C.POINTER(ldopf_options)]),
     "ldopf_solve": (C.c_int, [C.c_void_p, C.POINTER(ldopf_status)]),
     "ldopf_solve_noalloc": (C.c_int, [C.c_void_p, C.POINTER(ldopf_status)]),
+    "ldopf_solve_many": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(ldopf_status)]),
     "ldopf_reset": (C.c_int, [C.c_void_p]),
     "ldopf_warm_start": (C.c_int, [C.c_void_p, _d, _d, C.c_int64]),
     "ldopf_get_global": (C.c_int, [C.c_void_p, _d, C.c_int64]),

@@ -95,8 +95,11 @@ void build_device(ldopf_problem& h) {
     h.spin_limit = uint64_t(std::max(clock_khz, 1000)) * 1000ull * 5ull;
     h.tick_ms = 1.0 / double(std::max(clock_khz, 1));
 
-    for (int32_t n : lp.ns)
-        if (n > 255) fail(LDOPF_UNSUPPORTED, "subsystems with more than 255 variables are not supported on the device");
+    int32_t max_n = 1;
+    for (int32_t n : lp.ns) max_n = std::max(max_n, n);
+    if (max_n > kMaxSubsystemVars)
+        fail(LDOPF_UNSUPPORTED, "subsystems with more than " + std::to_string(kMaxSubsystemVars) +
+                                    " variables are not supported on the device");
     const int64_t S = lp.S;
     std::vector<int64_t> boff(S + 1, 0);
     for (int64_t i = 0; i < S; ++i) boff[i + 1] = boff[i] + int64_t(lp.ns[i]) * lp.ns[i];
@@ -132,6 +135,7 @@ void build_device(ldopf_problem& h) {
     pa.flags = h.flags.p;
     pa.tol_dep = 1e-10;
     pa.tol_rhs = 1e-9;
+    pa.max_n = max_n;
     hip_check(hipEventRecord(h.ev0, s), "event");
     hip_check(launch_precompute(pa, s), "precompute launch");
     hip_check(hipEventRecord(h.ev1, s), "event");
@@ -238,12 +242,13 @@ SweepArgs<T> sweep_args(ldopf_problem& h) {
     a.n_slots = h.plan.n_slots;
     a.check = h.opts.check_termination;
     a.P = h.plan.n_parts;
+    a.block = h.plan.block_threads;
     a.spin_limit = h.spin_limit;
     a.prof = h.opts.profile ? h.prof.p : nullptr;
     return a;
 }
 
-ldopf_problem* new_problem(const ldopf_options* opts, void* stream) {
+ldopf_problem* new_problem(const ldopf_options* opts, void* stream, SweepStatus* pinned_status = nullptr) {
     ldopf_options o;
     ldopf_default_options(&o);
     if (opts) o = *opts;
@@ -261,6 +266,13 @@ ldopf_problem* new_problem(const ldopf_options* opts, void* stream) {
         hip_check(hipEventCreate(&h->ev0), "event");
         hip_check(hipEventCreate(&h->ev1), "event");
         hip_check(hipEventCreateWithFlags(&h->done, hipEventDisableTiming), "event");
+        if (pinned_status) {
+            h->last_pinned = pinned_status;
+        } else {
+            hip_check(hipHostMalloc(reinterpret_cast<void**>(&h->last_pinned), sizeof(SweepStatus), hipHostMallocDefault),
+                      "pinned status");
+            h->own_pinned = true;
+        }
     } catch (...) {
         delete h;
         throw;
@@ -272,8 +284,10 @@ ldopf_problem* new_problem(const ldopf_options* opts, void* stream) {
 
 namespace ldopf {
 
-ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipStream_t stream) {
-    ldopf_problem* h = new_problem(&opts, stream);
+ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipStream_t stream, bool ordered_memory,
+                              SweepStatus* pinned_status) {
+    ldopf_problem* h = new_problem(&opts, stream, pinned_status);
+    if (ordered_memory) h->use_stream_ordered_memory(h->stream);
     try {
         h->lp = std::move(lp);
         build_device(*h);
@@ -301,7 +315,7 @@ size_t problem_sync_bytes(const ldopf_problem& h) {
            agg_words(h) * 8;
 }
 
-void problem_launch(ldopf_problem& h, const SyncWords* sw) {
+void problem_launch(ldopf_problem& h, const SyncWords* sw, bool cooperative) {
     if (h.in_flight) fail(LDOPF_INVALID_ARGUMENT, "a solve is already in flight on this handle");
     if (!sw) {
         const int64_t want = h.opts.history ? std::min<int64_t>(std::max<int64_t>(h.opts.max_iter, 1), int64_t(1) << 22) : 1;
@@ -319,12 +333,12 @@ void problem_launch(ldopf_problem& h, const SyncWords* sw) {
             args.bagg = sw->bagg;
             args.st = sw->st;
         }
-        return launch_sweep(args, h.plan.n_parts, h.plan.block_threads, size_t(h.plan.lds_bytes), h.stream);
+        return launch_sweep(args, h.plan.n_parts, h.plan.block_threads, size_t(h.plan.lds_bytes), h.stream, cooperative);
     };
     e = h.fp32 ? launch(sweep_args<float>(h)) : launch(sweep_args<double>(h));
     hip_check(e, "sweep launch");
     hip_check(hipEventRecord(h.ev1, h.stream), "event");
-    hip_check(hipMemcpyAsync(&h.last, sw ? sw->st : h.st.p, sizeof(h.last), hipMemcpyDeviceToHost, h.stream),
+    hip_check(hipMemcpyAsync(h.last_pinned, sw ? sw->st : h.st.p, sizeof(SweepStatus), hipMemcpyDeviceToHost, h.stream),
               "download status");
     hip_check(hipEventRecord(h.done, h.stream), "event");
     h.in_flight = true;
@@ -339,6 +353,7 @@ int problem_finish(ldopf_problem& h, ldopf_status* status) {
     if (!h.in_flight) fail(LDOPF_INVALID_ARGUMENT, "no solve in flight on this handle");
     h.in_flight = false;
     hip_check(hipEventSynchronize(h.done), "sweep");
+    h.last = *h.last_pinned;
     const SweepStatus st = h.last;
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, h.ev0, h.ev1), "event time");
@@ -636,6 +651,95 @@ int ldopf_solve_noalloc(ldopf_problem* h, ldopf_status* status) {
     });
     if (rc != LDOPF_OK && status) status->code = rc;
     return rc != LDOPF_OK ? rc : code;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One persistent launch for several problems (see ldopf_solve_many).
+template <typename T>
+void launch_many(const std::vector<ldopf_problem*>& hs, int block, size_t lds, hipStream_t stream) {
+    std::vector<SweepArgs<T>> args;
+    std::vector<int32_t> first{0};
+    for (ldopf_problem* h : hs) {
+        args.push_back(sweep_args<T>(*h));
+        first.push_back(first.back() + h->plan.n_parts);
+    }
+    DevBuf<SweepArgs<T>> d_args;
+    DevBuf<int32_t> d_first;
+    d_args.upload(args, stream, "upload problems");
+    d_first.upload(first, stream, "upload problems");
+    for (ldopf_problem* h : hs) hip_check(hipEventRecord(h->ev0, stream), "event");
+    hip_check(launch_sweep_many(args, d_args.p, d_first.p, first.back(), block, lds, stream), "sweep launch");
+    for (ldopf_problem* h : hs) {
+        hip_check(hipEventRecord(h->ev1, stream), "event");
+        hip_check(hipMemcpyAsync(h->last_pinned, h->st.p, sizeof(SweepStatus), hipMemcpyDeviceToHost, stream),
+                  "download status");
+        hip_check(hipEventRecord(h->done, stream), "event");
+        h->in_flight = true;
+    }
+    // the argument buffers are freed when they go out of scope: wait first
+    hip_check(hipStreamSynchronize(stream), "sweep");
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldopf_solve_many(ldopf_problem* const* hs, int32_t count, ldopf_status* statuses) {
+    int worst = LDOPF_OK;
+    const int rc = guard([&] {
+        need(hs, "problems");
+        if (count < 1 || count > 1024) fail(LDOPF_INVALID_ARGUMENT, "count must be in [1, 1024]");
+        std::vector<ldopf_problem*> v(hs, hs + count);
+        for (int32_t i = 0; i < count; ++i) {
+            need(v[i], "problem");
+            for (int32_t j = 0; j < i; ++j)
+                if (v[j] == v[i]) fail(LDOPF_INVALID_ARGUMENT, "a problem appears twice");
+            if (v[i]->in_flight) fail(LDOPF_INVALID_ARGUMENT, "a solve is already in flight on a problem");
+            if (v[i]->fp32 != v[0]->fp32 || v[i]->opts.residual_form != v[0]->opts.residual_form ||
+                v[i]->opts.profile != v[0]->opts.profile || v[i]->device != v[0]->device)
+                fail(LDOPF_INVALID_ARGUMENT, "the problems must share precision, residual form, profiling and device");
+        }
+        DeviceScope scope(v[0]->device);
+        // one launch size for all: the largest workgroup and LDS of any
+        // problem; each problem's workgroups run with their own size
+        int block = 0;
+        int64_t blocks = 0;
+        size_t lds = 0;
+        for (ldopf_problem* h : v) {
+            block = std::max(block, h->plan.block_threads);
+            blocks += h->plan.n_parts;
+            lds = std::max<size_t>(lds, size_t(h->plan.lds_bytes));
+        }
+        int lds_optin = 0, cus = 0;
+        hip_check(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, v[0]->device), "device attribute");
+        hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, v[0]->device), "device attribute");
+        if (lds > size_t(lds_optin)) fail(LDOPF_UNSUPPORTED, "the problems' workgroups need more LDS together than a workgroup has");
+        hip_check(prepare_sweep(v[0]->fp32, lds), "sweep LDS attribute");
+        int per_cu = 0;
+        hip_check(sweep_many_occupancy(v[0]->fp32, block, lds, &per_cu), "sweep occupancy");
+        if (int64_t(per_cu) * cus < blocks)
+            fail(LDOPF_UNSUPPORTED, "the problems' " + std::to_string(blocks) + " workgroups cannot be resident together (" +
+                                        std::to_string(per_cu) + " per CU); solve them in smaller groups");
+        for (ldopf_problem* h : v) {
+            hip_check(hipStreamSynchronize(h->stream), "earlier work of a problem");
+            const int64_t want = h->opts.history ? std::min<int64_t>(std::max<int64_t>(h->opts.max_iter, 1), int64_t(1) << 22) : 1;
+            if (int64_t(h->hist.count) < want * 4) h->hist.alloc(size_t(want) * 4, "history");
+            if (h->bagg.count < agg_words(*h)) h->bagg.alloc(agg_words(*h), "aggregated residual words");
+        }
+        if (v[0]->fp32)
+            launch_many<float>(v, block, lds, v[0]->stream);
+        else
+            launch_many<double>(v, block, lds, v[0]->stream);
+        for (int32_t i = 0; i < count; ++i) {
+            const int code = problem_finish(*v[i], statuses ? &statuses[i] : nullptr);
+            if (code < 0 && (worst >= 0 || code < worst)) worst = code;
+            if (code > 0 && worst == LDOPF_OK) worst = code;
+        }
+    });
+    return rc != LDOPF_OK ? rc : worst;
 }
 
 int ldopf_reset(ldopf_problem* h) {

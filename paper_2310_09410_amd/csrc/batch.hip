@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void precompute_batch_kernel(PrecomputeBatchAr
     const int64_t k = a.k0 + kc;
     const double* fs = a.n_load > 0 ? a.scale + k * a.n_load : nullptr;
     int bad = 0;
-    const int r = gs_project(lane, a.ns[s], a.ms[s], a.A + a.a_off[s], a.b + a.row_off[s], a.row_load + a.row_off[s],
+    const int r = gs_project<4>(lane, a.ns[s], a.ms[s], a.A + a.a_off[s], a.b + a.row_off[s], a.row_load + a.row_off[s],
                              a.row_wcol + a.row_off[s], fs, a.tol_dep, a.tol_rhs,
                              a.tmp_basis + kc * a.words + a.basis_off[s], sbeta[wv],
                              a.tmp_bbar + kc * a.nloc + a.loc_off[s], nullptr, &bad);
@@ -894,6 +894,7 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             pa.flags = flags_d.p;
             pa.tol_dep = 1e-10;
             pa.tol_rhs = 1e-9;
+            pa.max_n = *std::max_element(L.ns.begin(), L.ns.end());
             hip_check(launch_precompute(pa, s), "precompute");
             std::vector<int32_t> rank(S), flags(S);
             hip_check(hipMemcpyAsync(rank.data(), rank_d.p, S * 4, hipMemcpyDeviceToHost, s), "download ranks");

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "internal.h"
 
@@ -26,6 +27,7 @@ struct PrecomputeArgs {
     int32_t* flags; // out: 1 = inconsistent dependent row
     double tol_dep; // a row is dependent when its residual norm is below tol_dep * its norm
     double tol_rhs; // ... and then its right-hand side must be below tol_rhs * (1 + max |b_s|)
+    int32_t max_n;  // largest n_s (selects the kernel's columns per lane)
 };
 
 // Residual sums of the last kRing sweeps: every part's ([kRing][8][P]
@@ -91,6 +93,7 @@ struct SweepArgs {
     int64_t n_slots;
     int32_t check;
     int32_t P;
+    int32_t block;       // threads of the problem's workgroups (a multiple of 64, at most the launch's)
     uint64_t spin_limit; // wall-clock ticks an exchange wait may take
     double* prof;        // nullable: per-phase wall-clock ticks of every workgroup ([P][8])
     // residual balancing of rho (rho_update != 0)
@@ -114,7 +117,23 @@ hipError_t static_scratch(void** ptr);
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream);
 hipError_t prepare_sweep(bool fp32, size_t lds_bytes);
 hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu);
-hipError_t launch_sweep(const SweepArgs<double>& a, int grid, int block, size_t lds, hipStream_t stream);
-hipError_t launch_sweep(const SweepArgs<float>& a, int grid, int block, size_t lds, hipStream_t stream);
+// cooperative: the runtime guarantees that every workgroup is resident at
+// once (cooperative launches share one hardware queue, so they run one after
+// another); otherwise the caller guarantees it by admission (the serving
+// runtime counts compute units per XCD), and the sweeps of several problems
+// can run side by side. Either way a wait that cannot end is cut by the
+// bounded exchange waits (LDOPF_DEVICE_ERROR), not left to hang.
+hipError_t launch_sweep(const SweepArgs<double>& a, int grid, int block, size_t lds, hipStream_t stream,
+                        bool cooperative);
+hipError_t launch_sweep(const SweepArgs<float>& a, int grid, int block, size_t lds, hipStream_t stream,
+                        bool cooperative);
+// Several problems in one cooperative launch (sweep_many_kernel): host
+// copies of their arguments (for the per-problem resets), the same in device
+// memory, and the first block of each problem plus the total (count + 1).
+hipError_t sweep_many_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_sweep_many(const std::vector<SweepArgs<double>>& a, const SweepArgs<double>* dev_args,
+                             const int32_t* dev_first, int total_blocks, int block, size_t lds, hipStream_t stream);
+hipError_t launch_sweep_many(const std::vector<SweepArgs<float>>& a, const SweepArgs<float>* dev_args,
+                             const int32_t* dev_first, int total_blocks, int block, size_t lds, hipStream_t stream);
 
 }  // namespace ldopf

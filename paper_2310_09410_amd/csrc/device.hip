@@ -35,6 +35,7 @@
 #include <cmath>
 #include <cstdint>
 #include <mutex>
+#include <vector>
 
 #include "internal.h"
 #include "layout.h"
@@ -140,16 +141,18 @@ __device__ inline void st_agent(float* p, float v) {
 
 // ---------------------------------------------------------------------------
 // Operator precompute (FP64). One wave per subsystem, lane l owns columns
-// l, l + 64, l + 128, l + 192 (n_s <= 255); the work row lives in registers,
-// basis rows in global memory (each lane only touches its own columns).
+// l, l + 64, ... (NQ of them: 4 for n_s <= 256, 16 for n_s <= 1024); the work
+// row lives in registers, basis rows in global memory (each lane only
+// touches its own columns).
 
+template <int NQ>
 __global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs a) {
-    __shared__ double sbeta[4][256];
+    __shared__ double sbeta[4][64 * NQ];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t s = int64_t(blockIdx.x) * 4 + wv;
     if (s >= a.S) return;
     int bad = 0;
-    const int r = gs_project(lane, a.ns[s], a.ms[s], a.A + a.a_off[s], a.b + a.row_off[s], nullptr, nullptr, nullptr,
+    const int r = gs_project<NQ>(lane, a.ns[s], a.ms[s], a.A + a.a_off[s], a.b + a.row_off[s], nullptr, nullptr, nullptr,
                              a.tol_dep, a.tol_rhs, a.basis + a.basis_off[s], sbeta[wv], a.bbar + a.loc_off[s],
                              a.abar + a.basis_off[s], &bad);
     if (lane == 0) {
@@ -164,11 +167,10 @@ __global__ __launch_bounds__(256) void precompute_kernel(PrecomputeArgs a) {
 namespace {
 
 struct SubLds {
-    uint16_t row0;
-    uint8_t n, k;
-    uint16_t t0, mode;
+    uint16_t row0, t0;
+    uint16_t n, k;
+    uint16_t mode, pad;
     uint32_t w0;
-    uint32_t pad;
 };
 static_assert(sizeof(SubLds) == 16, "SubLds layout");
 
@@ -245,8 +247,9 @@ __device__ inline float in_vgpr(float x) {
     return x;
 }
 
+// One workgroup's whole solve: part `part` of the problem `a` describes.
 template <typename T, bool PROF, bool AGG>
-__global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
+__device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs<T>& a, const unsigned part) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int ok_lds;
     __shared__ int test_lds;  // 1 stop, 2 converged, 4 non-finite: the last test
@@ -256,8 +259,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     __shared__ double rule_mu, rule_tau;
     __shared__ int rule_period, rule_max;
     __shared__ double* rule_log;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    const PartInfo pi = a.parts[blockIdx.x];
+    // the problem's own workgroup size; in a launch of several problems the
+    // waves beyond it end here (a barrier waits only for running waves), so
+    // every problem runs exactly as in a launch of its own
+    const int tid = threadIdx.x, nt = a.block, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    if (tid >= nt) return;
+    const PartInfo pi = a.parts[part];
     const LdsLayout L = lds_layout(sizeof(T), uint32_t(pi.w_words), uint32_t(pi.n_row), uint32_t(pi.n_tk),
                                    uint32_t(pi.n_var), uint32_t(pi.n_sub), uint32_t(nw));
     T* W = reinterpret_cast<T*>(smem + in_vgpr(L.W));
@@ -314,7 +321,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     }
     for (int i = tid; i < pi.n_sub; i += nt) {
         const SubMeta m = a.subs[pi.sub_begin + i];
-        meta[i] = SubLds{m.row0, m.n, m.k, m.t0, m.mode, m.w0, 0u};
+        meta[i] = SubLds{m.row0, m.t0, m.n, m.k, m.mode, 0, m.w0};
     }
     for (int r = tid; r < R; r += nt) {
         const int canon = a.row_canon[pi.row_begin + r];
@@ -349,7 +356,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     for (int r = tid; r < R; r += nt) {
         const SubLds m = meta[rsub[r]];
         rwm[r] = make_uint2((m.w0 + uint32_t(r - m.row0)) | (uint32_t(m.t0) << 16),
-                            uint32_t(m.n) | ((uint32_t(m.k) | (uint32_t(m.mode) << 7)) << 8));
+                            uint32_t(m.n) | (uint32_t(m.k) << 12) | (uint32_t(m.mode) << 24));
     }
     for (int i = wv; i < pi.n_sub; i += nw) {
         const SubMeta m = a.subs[pi.sub_begin + i];
@@ -480,13 +487,13 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     // so that two 16-lane sums serve all five. Every part adds in the same
     // lane order, so every part takes the same decision.
     static_assert(kGroup == 16, "one lane row per group");
-    const bool leader = blockIdx.x % kGroup == 0;
-    const unsigned grp = blockIdx.x / kGroup, ngroups = (P + kGroup - 1) / kGroup;
+    const bool leader = part % kGroup == 0;
+    const unsigned grp = part / kGroup, ngroups = (P + kGroup - 1) / kGroup;
     // word B holds quantity 4 (lanes < 16) and, in the aggregated form, the
     // aggregated dual residual and dual norm (quantities 5, 6; lanes 16..47)
     constexpr int nqb = AGG ? 3 : 1, nq = 4 + nqb;
     const int qa = lane >> 4, gi = lane & 15, qb = 4 + qa;
-    const unsigned member = blockIdx.x + unsigned(gi);
+    const unsigned member = part + unsigned(gi);
     const bool mem_a = member < P, mem_b = mem_a && qa < nqb;
     const bool grp_a = unsigned(gi) < ngroups, grp_b = grp_a && qa < nqb;
     unsigned long long w1a = 0, w1b = 0, w2a = 0, w2b = 0;
@@ -578,7 +585,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                 const double f = rr > mu * ss ? tau : (ss > mu * rr ? 1.0 / tau : 1.0);
                 if (f != 1.0) {
                     rho_sched *= f;
-                    if (blockIdx.x == 0) {
+                    if (part == 0) {
                         double* lg = rule_log;
                         lg[2 * rho_changes] = double(sweep + kRhoLag);
                         lg[2 * rho_changes + 1] = rho_sched;
@@ -586,7 +593,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                     ++rho_changes;
                 }
             }
-            if (blockIdx.x == 0 && sweep <= a.hist_cap && ok_lds) {
+            if (part == 0 && sweep <= a.hist_cap && ok_lds) {
                 double* h = a.hist + (sweep - 1) * 4;
                 h[0] = pres;
                 h[1] = dres;
@@ -640,7 +647,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                 if (lane < 2) {
                     double q = 0.0;
                     for (int w = 0; w < n_work; ++w) q += aggw[w * 2 + lane];
-                    st_agent(ring1(done) + (5 + lane) * P + blockIdx.x, q);
+                    st_agent(ring1(done) + (5 + lane) * P + part, q);
                 }
             }
             __syncthreads();  // B2
@@ -675,7 +682,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             }
             sq_ = group_sum(sq_, 8);
             if (leader && done >= 1) group_sums(done);
-            if (lane < 40 && (lane & 7) == 0) st_agent(ring1(done + 1) + (lane >> 3) * P + blockIdx.x, sq_);
+            if (lane < 40 && (lane & 7) == 0) st_agent(ring1(done + 1) + (lane >> 3) * P + part, sq_);
             ++done;
         }
     } else {
@@ -762,8 +769,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
                     const T* wc = W + (rm.x & 0xffffu);
                     const T* tt = tb + (rm.x >> 16);
                     // four products per step, their eight loads issued together
-                    const int n_ = int(rm.y & 0xffu), K_ = int((rm.y >> 8) & 0x7fu);
-                    const bool mode1 = ((rm.y >> 15) & 1u) != 0;
+                    const int n_ = int(rm.y & 0xfffu), K_ = int((rm.y >> 12) & 0xfffu);
+                    const bool mode1 = ((rm.y >> 24) & 1u) != 0;
                     T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
                     int k = 0;
                     for (; k + 4 <= K_; k += 4) {
@@ -865,7 +872,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
             if (wv == tw && lane < 2) {
                 double q = 0.0;
                 for (int w = 0; w < n_work; ++w) q += aggw[w * 2 + lane];
-                st_agent(ring1(done) + (5 + lane) * P + blockIdx.x, q);
+                st_agent(ring1(done) + (5 + lane) * P + part, q);
             }
         }
         if (wv == tw && leader && done >= 1) {
@@ -895,7 +902,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         for (int v = tid; v < V; v += nt)
             if (a.var_writer[pi.var_begin + v]) a.x[a.var_gid[pi.var_begin + v]] = double(XL(fx)[v]);
     if (tid == 0 && (!ok || nonfinite)) atomicOr(&a.st->flags, (ok ? 0 : 1) | (nonfinite ? 2 : 0));
-    if (blockIdx.x == 0 && tid == 0) {
+    if (part == 0 && tid == 0) {
         if (result > 0)
             for (int q = 0; q < nq; ++q) d[q] = tot[q];
         a.st->iters = result;
@@ -907,7 +914,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
         a.st->eps_d = sqd * a.eps_abs + a.eps_rel * sqrt(AGG ? d[6] : d[4]);
         a.st->rho = result > 0 ? rho_of[result & 7] : a.rho;
     }
-    if (blockIdx.x == 0 && wv == tw && lane == 0) {
+    if (part == 0 && wv == tw && lane == 0) {
         // the changes whose first sweep was reached (a change decided near
         // the end may fall after the returned sweep)
         int64_t nch = 0;
@@ -918,8 +925,25 @@ __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
     }
     if (PROF && a.prof && tid == 0)
         for (int i = 0; i < 8; ++i)
-            if (i != 6) a.prof[blockIdx.x * 8 + i] = double(tprof[i]);
-    if (PROF && a.prof && wv == tw && lane == 0) a.prof[blockIdx.x * 8 + 6] = double(tw_prof);
+            if (i != 6) a.prof[part * 8 + i] = double(tprof[i]);
+    if (PROF && a.prof && wv == tw && lane == 0) a.prof[part * 8 + 6] = double(tw_prof);
+}
+
+template <typename T, bool PROF, bool AGG>
+__global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
+    sweep_body<T, PROF, AGG>(a, blockIdx.x);
+}
+
+// Several independent problems in one launch: problem p's workgroups are the
+// blocks first[p] .. first[p + 1] - 1, each running part blockIdx.x - first[p]
+// of that problem's sweep. The problems share nothing but the launch: each
+// has its own exchange words, residual rings, test and stop.
+template <typename T, bool PROF, bool AGG>
+__global__ __launch_bounds__(1024) void sweep_many_kernel(const SweepArgs<T>* args, const int32_t* first, int32_t count) {
+    int p = 0;
+    while (p + 1 < count && int32_t(blockIdx.x) >= first[p + 1]) ++p;
+    const SweepArgs<T> a = args[p];
+    sweep_body<T, PROF, AGG>(a, unsigned(int32_t(blockIdx.x) - first[p]));
 }
 
 // Before every sweep launch, on the same stream: every exchange word empty,
@@ -950,7 +974,11 @@ __global__ void reset_sync_kernel(T* bpart, int64_t n_bwords, double* rpart, int
 
 hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream) {
     const unsigned grid = unsigned((a.S + 3) / 4);
-    hipLaunchKernelGGL(precompute_kernel, dim3(grid), dim3(256), 0, stream, a);
+    if (a.max_n > 64 * 16) return hipErrorInvalidValue;
+    if (a.max_n <= 64 * 4)
+        hipLaunchKernelGGL(precompute_kernel<4>, dim3(grid), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(precompute_kernel<16>, dim3(grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -965,12 +993,38 @@ static const void* sweep_variant(bool prof, bool agg) {
     return prof ? sweep_ptr<T, true, false>() : sweep_ptr<T, false, false>();
 }
 
+template <typename T, bool PROF, bool AGG>
+static const void* many_ptr() {
+    return reinterpret_cast<const void*>(&sweep_many_kernel<T, PROF, AGG>);
+}
+
+template <typename T>
+static const void* many_variant(bool prof, bool agg) {
+    if (agg) return prof ? many_ptr<T, true, true>() : many_ptr<T, false, true>();
+    return prof ? many_ptr<T, true, false>() : many_ptr<T, false, false>();
+}
+
 hipError_t prepare_sweep(bool fp32, size_t lds_bytes) {
-    for (int v = 0; v < 4; ++v) {
-        const void* f = fp32 ? sweep_variant<float>(v & 1, v & 2) : sweep_variant<double>(v & 1, v & 2);
+    for (int v = 0; v < 8; ++v) {
+        const bool many = (v & 4) != 0;
+        const void* f = fp32 ? (many ? many_variant<float>(v & 1, v & 2) : sweep_variant<float>(v & 1, v & 2))
+                             : (many ? many_variant<double>(v & 1, v & 2) : sweep_variant<double>(v & 1, v & 2));
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
         if (e != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+hipError_t sweep_many_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu) {
+    int best = 1 << 30;
+    for (int v = 0; v < 4; ++v) {
+        const void* f = fp32 ? many_variant<float>(v & 1, v & 2) : many_variant<double>(v & 1, v & 2);
+        int n = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds_bytes);
+        if (e != hipSuccess) return e;
+        best = std::min(best, n);
+    }
+    *blocks_per_cu = best;
     return hipSuccess;
 }
 
@@ -989,26 +1043,57 @@ hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_p
 }
 
 template <typename T>
-static hipError_t launch_sweep_t(const SweepArgs<T>& a, int grid, int block, size_t lds, hipStream_t stream) {
+static hipError_t reset_sync(const SweepArgs<T>& a, hipStream_t stream) {
     const int64_t nb = 2 * std::max<int64_t>(a.n_slots, 1), nr = int64_t(kRing) * a.P * 8;
     const int64_t ng = int64_t(kRing) * 8 * kGroup;
     const int64_t na = a.bagg ? 4 * std::max<int64_t>(a.n_slots, 1) : 0;
     const unsigned rgrid = unsigned(std::min<int64_t>(256, (std::max(std::max(nb, nr), na) + 255) / 256));
     hipLaunchKernelGGL(reset_sync_kernel<T>, dim3(rgrid), dim3(256), 0, stream, a.bpart, nb, a.rpart, nr, a.gpart, ng,
                        a.bagg, na, a.st);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_sweep_t(const SweepArgs<T>& a, int grid, int block, size_t lds, hipStream_t stream,
+                                 bool cooperative) {
+    hipError_t e = reset_sync(a, stream);
     if (e != hipSuccess) return e;
     SweepArgs<T> copy = a;
     void* args[] = {&copy};
     const void* f = sweep_variant<T>(a.prof != nullptr, a.bagg != nullptr);
-    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), args, unsigned(lds), stream);
+    if (cooperative) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), args, unsigned(lds), stream);
+    return hipLaunchKernel(f, dim3(grid), dim3(block), args, lds, stream);
 }
 
-hipError_t launch_sweep(const SweepArgs<double>& a, int grid, int block, size_t lds, hipStream_t stream) {
-    return launch_sweep_t<double>(a, grid, block, lds, stream);
+hipError_t launch_sweep(const SweepArgs<double>& a, int grid, int block, size_t lds, hipStream_t stream,
+                        bool cooperative) {
+    return launch_sweep_t<double>(a, grid, block, lds, stream, cooperative);
 }
-hipError_t launch_sweep(const SweepArgs<float>& a, int grid, int block, size_t lds, hipStream_t stream) {
-    return launch_sweep_t<float>(a, grid, block, lds, stream);
+hipError_t launch_sweep(const SweepArgs<float>& a, int grid, int block, size_t lds, hipStream_t stream,
+                        bool cooperative) {
+    return launch_sweep_t<float>(a, grid, block, lds, stream, cooperative);
+}
+
+template <typename T>
+static hipError_t launch_many_t(const std::vector<SweepArgs<T>>& host_args, const SweepArgs<T>* dev_args,
+                                const int32_t* dev_first, int total_blocks, int block, size_t lds, hipStream_t stream) {
+    for (const SweepArgs<T>& a : host_args) {
+        const hipError_t e = reset_sync(a, stream);
+        if (e != hipSuccess) return e;
+    }
+    int32_t count = int32_t(host_args.size());
+    void* args[] = {const_cast<SweepArgs<T>**>(&dev_args), const_cast<int32_t**>(&dev_first), &count};
+    const void* f = many_variant<T>(host_args[0].prof != nullptr, host_args[0].bagg != nullptr);
+    return hipLaunchCooperativeKernel(f, dim3(total_blocks), dim3(block), args, unsigned(lds), stream);
+}
+
+hipError_t launch_sweep_many(const std::vector<SweepArgs<double>>& a, const SweepArgs<double>* dev_args,
+                             const int32_t* dev_first, int total_blocks, int block, size_t lds, hipStream_t stream) {
+    return launch_many_t<double>(a, dev_args, dev_first, total_blocks, block, lds, stream);
+}
+hipError_t launch_sweep_many(const std::vector<SweepArgs<float>>& a, const SweepArgs<float>* dev_args,
+                             const int32_t* dev_first, int total_blocks, int block, size_t lds, hipStream_t stream) {
+    return launch_many_t<float>(a, dev_args, dev_first, total_blocks, block, lds, stream);
 }
 
 }  // namespace ldopf

@@ -14,12 +14,14 @@ __device__ inline double gs_wave_sum(double v) {
     return v;
 }
 
-// One wave, one subsystem. Row i of A_s is As[i * n + c]; when fscale is
+// One wave, one subsystem of n <= 64 NQ variables (lane l owns columns l,
+// l + 64, ..., in registers). Row i of A_s is As[i * n + c]; when fscale is
 // given, a row carrying load row_load[i] has its right-hand side and its
 // coefficient in column row_wcol[i] multiplied by fscale[row_load[i]] (the
 // load scaling of a scenario). Writes the basis U (n x n), bbar (n) and, when
 // abar is not null, the dense Abar (n x n); returns the rank and sets *bad
 // when a dependent row has an inconsistent right-hand side.
+template <int NQ>
 __device__ inline int gs_project(int lane, int n, int m, const double* As, const double* bs, const int32_t* rload,
                           const int32_t* rwcol, const double* fscale, double tol_dep, double tol_rhs, double* U,
                           double* beta, double* bb, double* Ab, int* bad_out) {
@@ -37,10 +39,10 @@ __device__ inline int gs_project(int lane, int n, int m, const double* As, const
     for (int i = 0; i < m; ++i) bmax = fmax(bmax, fabs(bs[i] * scale_of(i)));
     int r = 0, bad = 0;
     for (int i = 0; i < m; ++i) {
-        double ar[4];
+        double ar[NQ];
         double nn = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const int c = lane + 64 * q;
             ar[q] = c < n ? coef(i, c) : 0.0;
             nn += ar[q] * ar[q];
@@ -51,13 +53,13 @@ __device__ inline int gs_project(int lane, int n, int m, const double* As, const
             for (int k = 0; k < r; ++k) {
                 double d = 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < NQ; ++q) {
                     const int c = lane + 64 * q;
                     if (c < n) d += ar[q] * U[int64_t(k) * n + c];
                 }
                 d = gs_wave_sum(d);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < NQ; ++q) {
                     const int c = lane + 64 * q;
                     if (c < n) ar[q] -= d * U[int64_t(k) * n + c];
                 }
@@ -66,12 +68,12 @@ __device__ inline int gs_project(int lane, int n, int m, const double* As, const
         }
         nn = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) nn += ar[q] * ar[q];
+        for (int q = 0; q < NQ; ++q) nn += ar[q] * ar[q];
         const double nr = sqrt(gs_wave_sum(nn));
         if (nrm0 > 0.0 && nr > tol_dep * nrm0 && r < n) {
             const double inv = 1.0 / nr;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 const int c = lane + 64 * q;
                 if (c < n) U[int64_t(r) * n + c] = ar[q] * inv;
             }
@@ -86,7 +88,7 @@ __device__ inline int gs_project(int lane, int n, int m, const double* As, const
         double best = -1.0;
         int bidx = 0x7fffffff;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const int c = lane + 64 * q;
             if (c < n) {
                 double res = 1.0;
@@ -102,20 +104,20 @@ __device__ inline int gs_project(int lane, int n, int m, const double* As, const
             const int oi = __shfl_xor(bidx, mm, 64);
             if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
         }
-        double ar[4];
+        double ar[NQ];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ar[q] = (lane + 64 * q) == bidx ? 1.0 : 0.0;
+        for (int q = 0; q < NQ; ++q) ar[q] = (lane + 64 * q) == bidx ? 1.0 : 0.0;
         for (int pass = 0; pass < 2; ++pass) {
             for (int k = 0; k < q2; ++k) {
                 double d = 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < NQ; ++q) {
                     const int c = lane + 64 * q;
                     if (c < n) d += ar[q] * U[int64_t(k) * n + c];
                 }
                 d = gs_wave_sum(d);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < NQ; ++q) {
                     const int c = lane + 64 * q;
                     if (c < n) ar[q] -= d * U[int64_t(k) * n + c];
                 }
@@ -123,17 +125,17 @@ __device__ inline int gs_project(int lane, int n, int m, const double* As, const
         }
         double nn = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) nn += ar[q] * ar[q];
+        for (int q = 0; q < NQ; ++q) nn += ar[q] * ar[q];
         const double inv = 1.0 / sqrt(gs_wave_sum(nn));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const int c = lane + 64 * q;
             if (c < n) U[int64_t(q2) * n + c] = ar[q] * inv;
         }
     }
     // bbar = Q' beta over the row-space rows
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int c = lane + 64 * q;
         if (c < n) {
             double acc = 0.0;
@@ -144,18 +146,20 @@ __device__ inline int gs_project(int lane, int n, int m, const double* As, const
     // dense Abar = Q'Q - I; entry (i, c) needs column i, owned by lane i % 64
     for (int i = 0; Ab && i < n; ++i) {
         const int owner = i & 63;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
         for (int k = 0; k < r; ++k) {
             const double mine = lane == owner ? U[int64_t(k) * n + i] : 0.0;
             const double ui = __shfl(mine, owner, 64);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 const int c = lane + 64 * q;
                 if (c < n) acc[q] += ui * U[int64_t(k) * n + c];
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const int c = lane + 64 * q;
             if (c < n) Ab[int64_t(i) * n + c] = acc[q] - (c == i ? 1.0 : 0.0);
         }

@@ -23,24 +23,36 @@ inline void hip_check(hipError_t e, const char* what) {
     fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// Owning device allocation.
+// Owning device allocation. With `ordered` set, allocation and release are
+// stream-ordered on that stream (hipMallocAsync / hipFreeAsync), so that
+// freeing one problem's memory does not wait for every kernel on the device
+// (hipFree does); the stream must outlive the buffer.
 template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t count = 0;
+    hipStream_t ordered = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (ordered)
+                (void)hipFreeAsync(p, ordered);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         count = 0;
     }
     void alloc(size_t n, const char* what) {
         release();
         const size_t bytes = std::max<size_t>(1, n) * sizeof(T);
-        hip_check(hipMalloc(reinterpret_cast<void**>(&p), bytes), what);
+        if (ordered)
+            hip_check(hipMallocAsync(reinterpret_cast<void**>(&p), bytes, ordered), what);
+        else
+            hip_check(hipMalloc(reinterpret_cast<void**>(&p), bytes), what);
         count = n;
     }
     void upload(const std::vector<T>& v, hipStream_t s, const char* what) {

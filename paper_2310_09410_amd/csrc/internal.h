@@ -47,6 +47,10 @@ ConsensusLP assemble_network(const ldopf_network& net);
 // Check an LP given directly (sizes, B_s invariants, bounds) and fill offsets.
 void finish_lp(ConsensusLP& lp);
 
+// Largest subsystem the device path takes (columns per lane of the
+// precompute, 12-bit fields of the sweep's packed row words).
+constexpr int kMaxSubsystemVars = 1024;
+
 // ---------------------------------------------------------------------------
 // Work partition of the persistent sweep kernel. Each part is one workgroup
 // that keeps its subsystems' operators and state resident in LDS.
@@ -54,16 +58,16 @@ void finish_lp(ConsensusLP& lp);
 // Per subsystem inside a part (device order). The first 16 bytes are what the
 // kernel keeps in LDS; basis/brow are only read while loading the part.
 struct SubMeta {
-    uint16_t row0;   // first local row (copy) of the subsystem inside the part
-    uint8_t n;       // n_s
-    uint8_t k;       // K_s rank-form vectors
-    uint16_t t0;     // first slot of the subsystem in the part's t buffer
-    uint16_t mode;   // 1: y = bbar + v - W'(W v); 0: y = bbar + W'(W v)
+    uint64_t basis;  // global word offset of the subsystem's n x n basis
     uint32_t w0;     // first operator word inside the part
     uint32_t canon;  // canonical subsystem index
-    uint64_t basis;  // global word offset of the subsystem's n x n basis
     uint32_t brow;   // first basis row taken (0 or rank)
-    uint32_t pad;
+    uint16_t row0;   // first local row (copy) of the subsystem inside the part
+    uint16_t n;      // n_s
+    uint16_t k;      // K_s rank-form vectors
+    uint16_t t0;     // first slot of the subsystem in the part's t buffer
+    uint16_t mode;   // 1: y = bbar + v - W'(W v); 0: y = bbar + W'(W v)
+    uint16_t pad;
 };
 static_assert(sizeof(SubMeta) == 32, "SubMeta layout");
 

@@ -64,7 +64,9 @@ Plan make_plan(const ConsensusLP& lp, const std::vector<int32_t>& rank, bool fp3
     int64_t rank_words = 0;
     for (int64_t s = 0; s < S; ++s) {
         const int32_t n = lp.ns[s], r = rank[s];
-        if (n > 255) fail(LDOPF_UNSUPPORTED, "subsystem " + std::to_string(s) + " has more than 255 variables");
+        if (n > kMaxSubsystemVars)
+            fail(LDOPF_UNSUPPORTED, "subsystem " + std::to_string(s) + " has more than " + std::to_string(kMaxSubsystemVars) +
+                                        " variables");
         // rank form: the row-space basis if it is the smaller side, else the
         // basis of its orthogonal complement
         mode[s] = (r <= n - r) ? 1 : 0;
@@ -110,8 +112,8 @@ Plan make_plan(const ConsensusLP& lp, const std::vector<int32_t>& rank, bool fp3
                 const int32_t n = lp.ns[s];
                 SubMeta m{};
                 m.row0 = uint16_t(row);
-                m.n = uint8_t(n);
-                m.k = uint8_t(K[s]);
+                m.n = uint16_t(n);
+                m.k = uint16_t(K[s]);
                 m.t0 = uint16_t(t);
                 m.mode = uint16_t(mode[s]);
                 m.w0 = wwords;

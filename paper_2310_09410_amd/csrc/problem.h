@@ -21,6 +21,10 @@ using ldopf::SweepStatus;
 
 struct ldopf_problem {
     SweepStatus last{};  // status read back by the last finished solve
+    // pinned host word the solve's status is copied into: a copy into
+    // pageable memory would block the launching thread until the sweep ends
+    SweepStatus* last_pinned = nullptr;
+    bool own_pinned = false;
     bool in_flight = false;
     ConsensusLP lp;
     ldopf_options opts{};
@@ -52,8 +56,26 @@ struct ldopf_problem {
     DevBuf<unsigned char> bpart;
     DevBuf<SweepStatus> st;
 
+    // every device buffer allocated and released in order on `s` (the
+    // serving runtime's slot streams, which outlive their problems)
+    void use_stream_ordered_memory(hipStream_t s) {
+        for (DevBuf<double>* q : {&A, &b, &basis, &abar, &bbar, &c, &lo, &hi, &cnt, &xs, &lam, &x, &hist, &rpart, &gpart,
+                                  &prof, &rholog, &bagg})
+            q->ordered = s;
+        for (DevBuf<int32_t>* q : {&ns, &ms, &rank_d, &flags, &row_canon, &var_gid, &var_slot, &var_slot_lo, &var_slot_hi})
+            q->ordered = s;
+        for (DevBuf<int64_t>* q : {&a_off, &row_off, &loc_off, &basis_off}) q->ordered = s;
+        for (DevBuf<uint16_t>* q : {&row_lvar, &row_sub, &var_copy_off, &var_copy_rows, &tk_sub}) q->ordered = s;
+        parts.ordered = s;
+        subs.ordered = s;
+        var_writer.ordered = s;
+        bpart.ordered = s;
+        st.ordered = s;
+    }
+
     ~ldopf_problem() {
         if (stream) (void)hipStreamSynchronize(stream);
+        if (own_pinned && last_pinned) (void)hipHostFree(last_pinned);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (done) (void)hipEventDestroy(done);
@@ -64,8 +86,11 @@ struct ldopf_problem {
 
 namespace ldopf {
 
-// Host LP -> handle with operators precomputed on the device (throws).
-ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipStream_t stream);
+// Host LP -> handle with operators precomputed on the device (throws). With
+// ordered_memory, every device buffer is allocated and freed in order on
+// `stream`, which must outlive the handle.
+ldopf_problem* problem_create(ConsensusLP&& lp, const ldopf_options& opts, hipStream_t stream,
+                              bool ordered_memory = false, SweepStatus* pinned_status = nullptr);
 // Where the sweep's synchronisation words live: the handle's own buffers,
 // or (allocation-free solve) carved from the static scratch array.
 struct SyncWords {
@@ -79,8 +104,9 @@ struct SyncWords {
 size_t problem_sync_bytes(const ldopf_problem& h);
 // Enqueue one solve (from the current state) on the handle's stream. With
 // sw, the sweep uses those words and nothing is allocated (the history goes
-// only into the buffer the handle already holds).
-void problem_launch(ldopf_problem& h, const SyncWords* sw = nullptr);
+// only into the buffer the handle already holds). cooperative = false only
+// where the caller's admission keeps every workgroup resident (serving).
+void problem_launch(ldopf_problem& h, const SyncWords* sw = nullptr, bool cooperative = true);
 // True when the enqueued solve has finished on the device.
 bool problem_ready(const ldopf_problem& h);
 // Wait for the enqueued solve, read its status; returns the ldopf_code.

@@ -11,8 +11,14 @@
 // sweeps can always be resident together. An admitted request gets its
 // operators precomputed and its solve launched on its slot's stream; its
 // state stays resident on the device until it finishes, when the results are
-// copied to host memory and its device memory and slot are released. Work of
-// different requests overlaps on the device. Latency = completion - submit.
+// copied to host memory and its device memory and slot are released. The
+// sweeps are launched as ordinary (not cooperative) launches, because
+// cooperative launches share one hardware queue and would run one after
+// another: the admission by compute units is what keeps every workgroup of
+// every running sweep resident, so the sweeps of different requests run side
+// by side. A request whose real plan needs more units than were admitted for
+// it (a rank-deficient subsystem changes the plan) is launched cooperatively.
+// Latency = completion - submit.
 
 #include <hip/hip_runtime.h>
 
@@ -66,6 +72,7 @@ struct ldopf_server {
     int64_t budget = 0;
     int32_t n_slots = 0;
     std::vector<hipStream_t> streams;
+    SweepStatus* pinned = nullptr;  // one pinned status word per slot
     std::vector<int64_t> slot_req;  // request id per slot, -1 free
     int dev = 0;
     int32_t units_per_xcd = kUnitsPerChip;
@@ -206,8 +213,9 @@ void ldopf_server::run() {
         if (!admit) continue;
         try {
             ConsensusLP lp = admit->lp;
-            admit->prob = problem_create(std::move(lp), admit->opts, streams[slot]);
-            problem_launch(*admit->prob);
+            admit->prob = problem_create(std::move(lp), admit->opts, streams[slot], true, pinned + slot);
+            const int32_t units = (admit->prob->plan.n_parts + 7) / 8;
+            problem_launch(*admit->prob, nullptr, units > admit->units);
         } catch (const Error& e) {
             std::lock_guard<std::mutex> lk(mu);
             admit->code = e.code;
@@ -251,9 +259,13 @@ int ldopf_server_create(int64_t hbm_budget_bytes, int32_t max_slots, ldopf_serve
                 hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream");
                 srv->streams.push_back(s);
             }
+            hip_check(hipHostMalloc(reinterpret_cast<void**>(&srv->pinned), sizeof(SweepStatus) * size_t(max_slots),
+                                    hipHostMallocDefault),
+                      "pinned status words");
             srv->worker = std::thread([srv] { srv->run(); });
         } catch (...) {
             for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
+            if (srv->pinned) (void)hipHostFree(srv->pinned);
             delete srv;
             throw;
         }
@@ -455,6 +467,7 @@ int ldopf_server_destroy(ldopf_server* srv) {
         }
         if (srv->worker.joinable()) srv->worker.join();
         for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
+        if (srv->pinned) (void)hipHostFree(srv->pinned);
         delete srv;
     });
 }

@@ -224,6 +224,15 @@ def ldopf_create(net: dict, opts: ldopf_options | None = None, stream=None) -> P
     return Problem(h)
 
 
+def ldopf_solve_many(problems, allow=(LDOPF_OK, LDOPF_NOT_CONVERGED)):
+    """Solve several problems together in one launch; returns their statuses."""
+    n = len(problems)
+    hs = (C.c_void_p * n)(*[p.h for p in problems])
+    st = (ldopf_status * n)()
+    _check(N.lib().ldopf_solve_many(hs, n, st), "ldopf_solve_many", allow=allow)
+    return list(st)
+
+
 def ldopf_create_lp(n, c, lo, hi, x_init, n_s, m_s, A, b, gidx, opts: ldopf_options | None = None,
                     stream=None) -> Problem:
     """Create from the consensus LP directly (see include/ldopf.h)."""

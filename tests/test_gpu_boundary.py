@@ -154,6 +154,26 @@ def test_delta_loads_shunts_taps(gpu, name, precision, tol):
         assert rel_err(lam, ref.lam) <= tol
 
 
+def test_delta_loads_shunts_taps_converged(gpu):
+    """The 13-bus feeder with delta loads, shunts and off-nominal taps (a
+    transformer or regulator is a line with per-phase tap ratios, as the
+    paper models transformers) to eps_rel = 1e-4: the oracle's stopping sweep
+    and state, and the objective against the LP optimum (HiGHS)."""
+    from oracle import admm, central, model
+    from synth import perturb_extras
+    P = gpu
+    net = perturb_extras(feeder("13"), 7)
+    prob = P.ldopf_create(net)
+    st = prob.solve()
+    ref = admm.solve(model.decompose(net))
+    assert st.converged and ref.converged and st.iterations == ref.iters
+    xs, lam = prob.get_local()
+    assert rel_err(prob.get_global(), ref.x) <= 1e-6
+    assert rel_err(xs, ref.xs) <= 1e-6 and rel_err(lam, ref.lam) <= 1e-6
+    f_lp, _, _ = central.solve_central(net)
+    assert abs(prob.objective() - f_lp) <= 1e-3 * max(1.0, abs(f_lp))
+
+
 def test_nonfinite_state(gpu):
     """A NaN warm start is refused; a finite state whose squares overflow
     stops the solve with LDOPF_NUMERICAL at the first sweep whose residual
