@@ -247,9 +247,15 @@ __device__ inline float in_vgpr(float x) {
     return x;
 }
 
+// Compile-time variants of the sweep: bit 0 per-phase profiling, bit 1 the
+// aggregated residual form, bit 2 residual balancing of rho (without it rho
+// is a constant of the launch).
+constexpr int kModeProf = 1, kModeAgg = 2, kModeRho = 4;
+
 // One workgroup's whole solve: part `part` of the problem `a` describes.
-template <typename T, bool PROF, bool AGG>
+template <typename T, int MODE>
 __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs<T>& a, const unsigned part) {
+    constexpr bool PROF = (MODE & kModeProf) != 0, AGG = (MODE & kModeAgg) != 0, RHO = (MODE & kModeRho) != 0;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int ok_lds;
     __shared__ int test_lds;  // 1 stop, 2 converged, 4 non-finite: the last test
@@ -302,8 +308,9 @@ __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs
     // rho of the sweep being computed (sweep done + 1) and 1/rho of the next
     // one, whose global update the partial sums published in this sweep feed
     // (they differ only where residual balancing changes rho)
-    double rho_c = in_vgpr(a.rho);
-    T rho_cT = in_vgpr(T(a.rho)), irho_c = in_vgpr(T(1.0 / a.rho)), irho_n = irho_c;
+    double rho_c = RHO ? in_vgpr(a.rho) : a.rho;
+    T rho_cT = RHO ? in_vgpr(T(a.rho)) : T(a.rho);
+    T irho_c = RHO ? in_vgpr(T(1.0 / a.rho)) : T(1.0 / a.rho), irho_n = irho_c;
     const int R = pi.n_row, V = pi.n_var, TK = pi.n_tk;
     const unsigned P = unsigned(a.P);
     const int64_t ns = a.n_slots;
@@ -311,8 +318,8 @@ __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs
 
     // ---- load this part into LDS
     if (tid == 0) ok_lds = 1;
-    if (tid < 8) rho_of[tid] = a.rho;
-    if (tid == 0) {
+    if (RHO && tid < 8) rho_of[tid] = a.rho;
+    if (RHO && tid == 0) {
         rule_mu = a.rho_mu;
         rule_tau = a.rho_tau;
         rule_period = a.rho_update ? a.rho_period : 0;
@@ -579,7 +586,7 @@ __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs
             const int stop = nf || (a.check && cv);
             test_lds = (stop ? 1 : 0) | (cv ? 2 : 0) | (nf ? 4 : 0);
             const int period = rule_period;
-            if (may_change && !stop && period > 0 && sweep % period == 0 && rho_changes < rule_max && eps_p > 0.0 &&
+            if (RHO && may_change && !stop && period > 0 && sweep % period == 0 && rho_changes < rule_max && eps_p > 0.0 &&
                 eps_d > 0.0) {
                 const double rr = pres / eps_p, ss = dres / eps_d, mu = rule_mu, tau = rule_tau;
                 const double f = rr > mu * ss ? tau : (ss > mu * rr ? 1.0 / tau : 1.0);
@@ -630,7 +637,7 @@ __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs
             }
             // rho of sweep done + 2 (a change decided from the test of sweep
             // done - 2), read by the row waves after B1
-            if (lane == 0) rho_of[(done + 2) & 7] = rho_sched;
+            if (RHO && lane == 0) rho_of[(done + 2) & 7] = rho_sched;
             __syncthreads();  // B1
             if (ok_lds == 0) {
                 ok = false;
@@ -721,8 +728,8 @@ __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs
             }
             // rho of the next sweep, whose global update this sweep's
             // published partial sums feed
-            const double rho_n = in_vgpr(rho_of[(done + 2) & 7]);
-            irho_n = in_vgpr(T(1.0 / rho_n));
+            const double rho_n = RHO ? in_vgpr(rho_of[(done + 2) & 7]) : a.rho;
+            if (RHO) irho_n = in_vgpr(T(1.0 / rho_n));
             stamp(0);
             // v = B_s x + lambda_s / rho
             const T* lc = LAM(cur);
@@ -845,9 +852,11 @@ __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs
                     }
                 }
             }
-            rho_c = rho_n;
-            rho_cT = in_vgpr(T(rho_n));
-            irho_c = irho_n;
+            if (RHO) {
+                rho_c = rho_n;
+                rho_cT = in_vgpr(T(rho_n));
+                irho_c = irho_n;
+            }
             stamp(4);
             ++done;
             cur = nx;
@@ -912,9 +921,9 @@ __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs
         a.st->dres = sqrt(AGG ? d[5] : d[1]);
         a.st->eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
         a.st->eps_d = sqd * a.eps_abs + a.eps_rel * sqrt(AGG ? d[6] : d[4]);
-        a.st->rho = result > 0 ? rho_of[result & 7] : a.rho;
+        a.st->rho = (RHO && result > 0) ? rho_of[result & 7] : a.rho;
     }
-    if (part == 0 && wv == tw && lane == 0) {
+    if (RHO && part == 0 && wv == tw && lane == 0) {
         // the changes whose first sweep was reached (a change decided near
         // the end may fall after the returned sweep)
         int64_t nch = 0;
@@ -929,21 +938,21 @@ __device__ __attribute__((always_inline)) inline void sweep_body(const SweepArgs
     if (PROF && a.prof && wv == tw && lane == 0) a.prof[part * 8 + 6] = double(tw_prof);
 }
 
-template <typename T, bool PROF, bool AGG>
+template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void sweep_kernel(SweepArgs<T> a) {
-    sweep_body<T, PROF, AGG>(a, blockIdx.x);
+    sweep_body<T, MODE>(a, blockIdx.x);
 }
 
 // Several independent problems in one launch: problem p's workgroups are the
 // blocks first[p] .. first[p + 1] - 1, each running part blockIdx.x - first[p]
 // of that problem's sweep. The problems share nothing but the launch: each
 // has its own exchange words, residual rings, test and stop.
-template <typename T, bool PROF, bool AGG>
+template <typename T, int MODE>
 __global__ __launch_bounds__(1024) void sweep_many_kernel(const SweepArgs<T>* args, const int32_t* first, int32_t count) {
     int p = 0;
     while (p + 1 < count && int32_t(blockIdx.x) >= first[p + 1]) ++p;
     const SweepArgs<T> a = args[p];
-    sweep_body<T, PROF, AGG>(a, unsigned(int32_t(blockIdx.x) - first[p]));
+    sweep_body<T, MODE>(a, unsigned(int32_t(blockIdx.x) - first[p]));
 }
 
 // Before every sweep launch, on the same stream: every exchange word empty,
@@ -982,33 +991,40 @@ hipError_t launch_precompute(const PrecomputeArgs& a, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <typename T, bool PROF, bool AGG>
+template <typename T, int MODE>
 static const void* sweep_ptr() {
-    return reinterpret_cast<const void*>(&sweep_kernel<T, PROF, AGG>);
+    return reinterpret_cast<const void*>(&sweep_kernel<T, MODE>);
 }
 
-template <typename T>
-static const void* sweep_variant(bool prof, bool agg) {
-    if (agg) return prof ? sweep_ptr<T, true, true>() : sweep_ptr<T, false, true>();
-    return prof ? sweep_ptr<T, true, false>() : sweep_ptr<T, false, false>();
-}
-
-template <typename T, bool PROF, bool AGG>
+template <typename T, int MODE>
 static const void* many_ptr() {
-    return reinterpret_cast<const void*>(&sweep_many_kernel<T, PROF, AGG>);
+    return reinterpret_cast<const void*>(&sweep_many_kernel<T, MODE>);
 }
 
 template <typename T>
-static const void* many_variant(bool prof, bool agg) {
-    if (agg) return prof ? many_ptr<T, true, true>() : many_ptr<T, false, true>();
-    return prof ? many_ptr<T, true, false>() : many_ptr<T, false, false>();
+static const void* sweep_variant(int mode) {
+    static const void* const table[8] = {sweep_ptr<T, 0>(), sweep_ptr<T, 1>(), sweep_ptr<T, 2>(), sweep_ptr<T, 3>(),
+                                         sweep_ptr<T, 4>(), sweep_ptr<T, 5>(), sweep_ptr<T, 6>(), sweep_ptr<T, 7>()};
+    return table[mode & 7];
+}
+
+template <typename T>
+static const void* many_variant(int mode) {
+    static const void* const table[8] = {many_ptr<T, 0>(), many_ptr<T, 1>(), many_ptr<T, 2>(), many_ptr<T, 3>(),
+                                         many_ptr<T, 4>(), many_ptr<T, 5>(), many_ptr<T, 6>(), many_ptr<T, 7>()};
+    return table[mode & 7];
+}
+
+template <typename T>
+static int sweep_mode(const SweepArgs<T>& a) {
+    return (a.prof ? kModeProf : 0) | (a.bagg ? kModeAgg : 0) | (a.rho_update ? kModeRho : 0);
 }
 
 hipError_t prepare_sweep(bool fp32, size_t lds_bytes) {
-    for (int v = 0; v < 8; ++v) {
-        const bool many = (v & 4) != 0;
-        const void* f = fp32 ? (many ? many_variant<float>(v & 1, v & 2) : sweep_variant<float>(v & 1, v & 2))
-                             : (many ? many_variant<double>(v & 1, v & 2) : sweep_variant<double>(v & 1, v & 2));
+    for (int v = 0; v < 16; ++v) {
+        const bool many = (v & 8) != 0;
+        const void* f = fp32 ? (many ? many_variant<float>(v) : sweep_variant<float>(v))
+                             : (many ? many_variant<double>(v) : sweep_variant<double>(v));
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
         if (e != hipSuccess) return e;
     }
@@ -1017,8 +1033,8 @@ hipError_t prepare_sweep(bool fp32, size_t lds_bytes) {
 
 hipError_t sweep_many_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu) {
     int best = 1 << 30;
-    for (int v = 0; v < 4; ++v) {
-        const void* f = fp32 ? many_variant<float>(v & 1, v & 2) : many_variant<double>(v & 1, v & 2);
+    for (int v = 0; v < 8; ++v) {
+        const void* f = fp32 ? many_variant<float>(v) : many_variant<double>(v);
         int n = 0;
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds_bytes);
         if (e != hipSuccess) return e;
@@ -1031,8 +1047,8 @@ hipError_t sweep_many_occupancy(bool fp32, int block, size_t lds_bytes, int* blo
 hipError_t sweep_occupancy(bool fp32, int block, size_t lds_bytes, int* blocks_per_cu) {
     // the fewest co-resident workgroups of any variant the handle may launch
     int best = 1 << 30;
-    for (int v = 0; v < 4; ++v) {
-        const void* f = fp32 ? sweep_variant<float>(v & 1, v & 2) : sweep_variant<double>(v & 1, v & 2);
+    for (int v = 0; v < 8; ++v) {
+        const void* f = fp32 ? sweep_variant<float>(v) : sweep_variant<double>(v);
         int n = 0;
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds_bytes);
         if (e != hipSuccess) return e;
@@ -1060,7 +1076,7 @@ static hipError_t launch_sweep_t(const SweepArgs<T>& a, int grid, int block, siz
     if (e != hipSuccess) return e;
     SweepArgs<T> copy = a;
     void* args[] = {&copy};
-    const void* f = sweep_variant<T>(a.prof != nullptr, a.bagg != nullptr);
+    const void* f = sweep_variant<T>(sweep_mode(a));
     if (cooperative) return hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), args, unsigned(lds), stream);
     return hipLaunchKernel(f, dim3(grid), dim3(block), args, lds, stream);
 }
@@ -1083,7 +1099,11 @@ static hipError_t launch_many_t(const std::vector<SweepArgs<T>>& host_args, cons
     }
     int32_t count = int32_t(host_args.size());
     void* args[] = {const_cast<SweepArgs<T>**>(&dev_args), const_cast<int32_t**>(&dev_first), &count};
-    const void* f = many_variant<T>(host_args[0].prof != nullptr, host_args[0].bagg != nullptr);
+    // one variant for all: residual balancing if any problem asks for it (a
+    // problem without it never changes rho there), the rest shared by all
+    int mode = 0;
+    for (const SweepArgs<T>& a : host_args) mode |= sweep_mode(a);
+    const void* f = many_variant<T>(mode);
     return hipLaunchCooperativeKernel(f, dim3(total_blocks), dim3(block), args, unsigned(lds), stream);
 }
 

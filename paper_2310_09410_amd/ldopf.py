@@ -113,7 +113,10 @@ class Problem:
         self.h = handle
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may be gone already
+            pass
 
     def close(self):
         if getattr(self, "h", None):
@@ -262,7 +265,10 @@ class Batch:
         self.h = handle
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may be gone already
+            pass
 
     def close(self):
         if getattr(self, "h", None):
@@ -342,7 +348,10 @@ class Server:
         self.h = h
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may be gone already
+            pass
 
     def close(self):
         if getattr(self, "h", None):
