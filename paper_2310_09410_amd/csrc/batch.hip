@@ -753,12 +753,17 @@ int64_t run_to_done(ldopf_batch& h, double* ms_out) {
     if (h.opts.max_iter == 0) return 0;
     build_graph(h);
     int64_t ctrl[2] = {0, 0};
+    hip_check(hipMemcpyAsync(ctrl, h.ctrl.p, sizeof(ctrl), hipMemcpyDeviceToHost, h.stream), "download control");
+    hip_check(hipStreamSynchronize(h.stream), "download control");
     hip_check(hipEventRecord(h.ev0, h.stream), "event");
     for (;;) {
+        const int64_t before = ctrl[0];
         hip_check(hipGraphLaunch(h.exec, h.stream), "graph launch");
         hip_check(hipMemcpyAsync(ctrl, h.ctrl.p, sizeof(ctrl), hipMemcpyDeviceToHost, h.stream), "download control");
         hip_check(hipStreamSynchronize(h.stream), "batch sweep");
         if (ctrl[1]) break;
+        // every sweep of a graph that did not finish the batch advances the count
+        if (ctrl[0] != before + h.graph_sweeps) fail(LDOPF_DEVICE_ERROR, "the batched sweep count did not advance");
     }
     hip_check(hipEventRecord(h.ev1, h.stream), "event");
     hip_check(hipEventSynchronize(h.ev1), "event");
