@@ -51,6 +51,7 @@ constexpr int kTile = 64;  // scenarios per wave
 constexpr int kZS = 80;    // LDS row stride (floats) of the local update
 constexpr int kVPW = 4;    // variables per wave in the global update
 constexpr int kRedBlocks = 8;  // reduction blocks per scenario tile
+constexpr int kKB = 1;         // operator rows per load batch of the per-scenario class
 
 struct PrecomputeBatchArgs {
     int64_t S, nloc, words;
@@ -280,11 +281,11 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
     float* Ys = Vs + a.nmax * kZS;          // [nmax][kZS]
     float* Ts = Ys + a.nmax * kZS;          // [kmax][kZS]
     float* As = Ts + a.kmax * kZS;          // [kmax * nmax] shared rank-form rows
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x, lane_id = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int Bp = a.Bp;
-    const int sc = blockIdx.y * kTile + lane;
-    const bool on = a.active[sc] != 0;
+    const int sc_id = blockIdx.y * kTile + lane_id;
+    const bool on = a.active[sc_id] != 0;
     // a tile whose scenarios have all stopped is skipped (its partial rows
     // are not read: the test runs only for active scenarios)
     if (__syncthreads_or(on) == 0) return;
@@ -294,11 +295,18 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
     const CPtr<int32_t> chunk_off = as_const(a.chunk_off);
     const CPtr<int32_t> meta = as_const(reinterpret_cast<const int32_t*>(a.meta));
     const CPtr<int32_t> gidx = as_const(a.gidx);
+    bool prev_shared = false;  // the last subsystem was of the shared-operator class
     for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
         const int q1 = chunk_off[c + 1];
         int q = chunk_off[c];
         LocalMeta m = load_meta(meta, q);
         for (; q < q1; ++q) {
+            // opaque copies of the lane's indices, so that per-lane addresses
+            // are formed again in each subsystem instead of being held across
+            // the loop (they would not fit the register budget)
+            int lane_o = lane_id, sc_o = sc_id;
+            asm volatile("" : "+v"(lane_o), "+v"(sc_o));
+            const int lane = lane_o, sc = sc_o;
             // the next subsystem's metadata is loaded one subsystem ahead
             const LocalMeta mn = load_meta(meta, q + 1 < q1 ? q + 1 : q);
             const int n = m.n;
@@ -321,20 +329,19 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
                 xo[r] = XSb[o];
                 bb[r] = BBb[o];
             }
+            float y[RPW];
             if (m.cls == 0) {
                 const float* Ab = a.ash + m.off;
                 for (int i = tid; i < m.K * n; i += 256) As[i] = Ab[i];
-            }
 #pragma unroll
-            for (int r = 0; r < RPW; ++r) {
-                const int j = wv + 4 * r;
-                if (j < n) {
-                    Vs[j * kZS + lane] = z[r] + l0[r] * irho;
-                    Ys[j * kZS + lane] = bb[r];
+                for (int r = 0; r < RPW; ++r) {
+                    const int j = wv + 4 * r;
+                    if (j < n) {
+                        Vs[j * kZS + lane] = z[r] + l0[r] * irho;
+                        Ys[j * kZS + lane] = bb[r];
+                    }
                 }
-            }
-            __syncthreads();
-            if (m.cls == 0) {
+                __syncthreads();
                 // T = W V: (16-row tile of W, 16-scenario tile) products spread
                 // over the four waves
                 const int K = m.K, mode = m.mode;
@@ -378,46 +385,110 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
                         }
                     }
                 }
-            } else {
-                const int K = m.K, mode = m.mode;
-                const float* Wb = a.W + m.off * Bp;
-                const int nB = n * Bp;
-                for (int k = wv; k < K; k += 4) {
-                    const int o0 = k * nB + sc;
-                    float t[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    int j = 0;
-                    for (; j + 8 <= n; j += 8) {
-                        float w[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) w[u] = Wb[o0 + (j + u) * Bp];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) t[u] += w[u] * Vs[(j + u) * kZS + lane];
-                    }
-                    for (; j < n; ++j) t[0] += Wb[o0 + j * Bp] * Vs[j * kZS + lane];
-                    Ts[k * kZS + lane] = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
-                }
                 __syncthreads();
-                for (int j = wv; j < n; j += 4) {
-                    const int o0 = j * Bp + sc;
-                    float u[4] = {0.f, 0.f, 0.f, 0.f};
-                    int k = 0;
-                    for (; k + 4 <= K; k += 4) {
-                        float w[4];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) w[e] = Wb[o0 + (k + e) * nB];
+                for (int r = 0; r < RPW; ++r) y[r] = Ys[min(wv + 4 * r, n - 1) * kZS + lane];
+                prev_shared = true;
+            } else {
+                // Per-scenario operator, on the wave's own rows j = wv + 4 r with
+                // v_j in registers: each wave adds its rows' terms of t = W v
+                // for every k (partial sums in LDS, over the rows of v and y,
+                // which this class does not use), then, after one barrier, t_k
+                // = the four partials in wave order and y_j = bbar_j + v_j -
+                // sum_k W_kj t_k (mode 1) or bbar_j + sum_k W_kj t_k (mode 0).
+                // W is read in batches of kKB operator rows x RPW rows, all
+                // loads of a batch issued together and the next batch issued
+                // before the current one is used.
+                const int K = m.K, mode = m.mode;
+                float* Tp = Vs;  // [4][K][64]
+                // the shared class before reads its y rows after its last
+                // barrier: wait for every wave before the partials overwrite them
+                if (prev_shared) __syncthreads();
+                prev_shared = false;
+                // v_j = z_j + lambda_j / rho, recomputed where used; zero past n_s
+                auto vj = [&](int r) -> float { return (wv + 4 * r < n) ? z[r] + l0[r] * irho : 0.f; };
+                if (K == 0) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) u[e] += w[e] * Ts[(k + e) * kZS + lane];
+                    for (int r = 0; r < RPW; ++r) y[r] = mode ? bb[r] + vj(r) : bb[r];
+                } else {
+                    // W row (k, j) at (k n_s + j) Bp + sc. A batch takes rows
+                    // k0 .. k0 + kKB - 1 of W for the wave's RPW rows j; rows past
+                    // the subsystem (k >= K, or j >= n_s) read the last row that
+                    // exists again (a cache hit), so every batch issues the same
+                    // loads and stays inside the subsystem's operator
+                    const char* Wc = reinterpret_cast<const char*>(a.W + m.off * Bp);
+                    const uint32_t Bp4 = uint32_t(Bp) * 4u;
+                    const uint32_t jo = uint32_t(sc) * 4u;
+                    const int nr = max(1, (n - wv + 3) / 4);  // the wave's rows
+                    auto issue = [&](float (&w)[kKB][RPW], int k0) {
+#pragma unroll
+                        for (int kb = 0; kb < kKB; ++kb)
+#pragma unroll
+                            for (int r = 0; r < RPW; ++r) {
+                                // uniform base (scalar registers) + the lane's 32-bit offset
+                                const int k = min(k0 + kb, K - 1), j = min(wv + 4 * min(r, nr - 1), n - 1);
+                                const char* base = Wc + uint32_t(k * n + j) * Bp4;
+                                w[kb][r] = *reinterpret_cast<const float*>(base + jo);
+                            }
+                    };
+                    auto t_use = [&](const float (&w)[kKB][RPW], int k0) {
+#pragma unroll
+                        for (int kb = 0; kb < kKB; ++kb) {
+                            float t = 0.f;
+#pragma unroll
+                            for (int r = 0; r < RPW; ++r) t += w[kb][r] * vj(r);
+                            if (k0 + kb < K) Tp[(wv * K + k0 + kb) * 64 + lane] = t;
+                        }
+                    };
+                    float acc[RPW];
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) acc[r] = 0.f;
+                    auto y_use = [&](const float (&w)[kKB][RPW], int k0) {
+#pragma unroll
+                        for (int kb = 0; kb < kKB; ++kb) {
+                            const int k = min(k0 + kb, K - 1);
+                            const float tk = ((Tp[(0 * K + k) * 64 + lane] + Tp[(1 * K + k) * 64 + lane]) +
+                                              Tp[(2 * K + k) * 64 + lane]) +
+                                             Tp[(3 * K + k) * 64 + lane];
+                            const float g = k0 + kb < K ? tk : 0.f;
+#pragma unroll
+                            for (int r = 0; r < RPW; ++r) acc[r] += w[kb][r] * g;
+                        }
+                    };
+                    // loads are issued on every path (never behind a branch),
+                    // so the wait before each use counts only older batches
+                    float wa[kKB][RPW], wb[kKB][RPW];
+                    issue(wa, 0);
+                    for (int k0 = 0;; k0 += 2 * kKB) {
+                        issue(wb, k0 + kKB);
+                        t_use(wa, k0);
+                        if (k0 + kKB >= K) break;
+                        issue(wa, k0 + 2 * kKB);
+                        t_use(wb, k0 + kKB);
+                        if (k0 + 2 * kKB >= K) break;
                     }
-                    for (; k < K; ++k) u[0] += Wb[o0 + k * nB] * Ts[k * kZS + lane];
-                    const float acc = (u[0] + u[1]) + (u[2] + u[3]);
-                    const float vj = Vs[j * kZS + lane];
-                    const float bj = Ys[j * kZS + lane];
-                    Ys[j * kZS + lane] = mode ? bj + (vj - acc) : bj + acc;
+                    if (K <= kKB) {
+                        // the one batch is still held in wa
+                        __syncthreads();
+                        y_use(wa, 0);
+                    } else {
+                        issue(wa, 0);
+                        __syncthreads();
+                        for (int k0 = 0;; k0 += 2 * kKB) {
+                            issue(wb, k0 + kKB);
+                            y_use(wa, k0);
+                            if (k0 + kKB >= K) break;
+                            issue(wa, k0 + 2 * kKB);
+                            y_use(wb, k0 + kKB);
+                            if (k0 + 2 * kKB >= K) break;
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) y[r] = mode ? bb[r] + (vj(r) - acc[r]) : bb[r] + acc[r];
+                    // every wave has read the partials before the next subsystem writes them
+                    __syncthreads();
                 }
             }
-            // the shared class wrote y by tiles: wait for every wave; the
-            // per-scenario class wrote each wave's own rows
-            if (m.cls == 0) __syncthreads();
             // dual update and residual sums on the wave's own rows
             float* XSw = a.XS + row0 * Bp;
             float* LAMw = a.LAM + row0 * Bp;
@@ -426,15 +497,15 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
                 const int j = wv + 4 * r;
                 if (j < n && on) {
                     const int o = j * Bp + sc;
-                    const float y = Ys[j * kZS + lane];
-                    const float l1 = l0[r] + rho * (z[r] - y);
-                    XSw[o] = y;
+                    const float yj = y[r];
+                    const float l1 = l0[r] + rho * (z[r] - yj);
+                    XSw[o] = yj;
                     LAMw[o] = l1;
-                    const double dz = double(z[r]) - double(y), dx = double(y) - double(xo[r]);
+                    const double dz = double(z[r]) - double(yj), dx = double(yj) - double(xo[r]);
                     p0 += dz * dz;
                     p1 += dx * dx;
                     p2 += double(z[r]) * double(z[r]);
-                    p3 += double(y) * double(y);
+                    p3 += double(yj) * double(yj);
                     p4 += double(l1) * double(l1);
                 }
             }
@@ -444,11 +515,11 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
     // the four waves' sums of each scenario, in wave order
     __syncthreads();
     double* red = reinterpret_cast<double*>(sm);  // [4][5][64]
-    red[(wv * 5 + 0) * 64 + lane] = p0;
-    red[(wv * 5 + 1) * 64 + lane] = p1;
-    red[(wv * 5 + 2) * 64 + lane] = p2;
-    red[(wv * 5 + 3) * 64 + lane] = p3;
-    red[(wv * 5 + 4) * 64 + lane] = p4;
+    red[(wv * 5 + 0) * 64 + lane_id] = p0;
+    red[(wv * 5 + 1) * 64 + lane_id] = p1;
+    red[(wv * 5 + 2) * 64 + lane_id] = p2;
+    red[(wv * 5 + 3) * 64 + lane_id] = p3;
+    red[(wv * 5 + 4) * 64 + lane_id] = p4;
     __syncthreads();
     double* out = a.part + int64_t(blockIdx.x) * 5 * Bp;
     for (int e = tid; e < 5 * 64; e += 256) {
@@ -599,6 +670,7 @@ struct ldopf_batch {
     int32_t graph_sweeps = 16;
     int32_t grid = 0;         // local-update blocks per scenario tile
     int32_t nmax = 1, kmax = 1, rpw = 10;
+    int64_t w_words = 0;  // FP32 words of the per-scenario operators (without the padding)
     double precompute_ms = 0.0;
     int64_t n_mf = 0, n_vec = 0;
     std::vector<int32_t> chunk_off_h;
@@ -606,6 +678,7 @@ struct ldopf_batch {
 
     DevBuf<int32_t> ns, gidx, var_off, var_copy, chunk_off, cls, vK;
     DevBuf<LocalMeta> meta;
+    std::vector<LocalMeta> meta_h;  // per subsystem, in subsystem order
     DevBuf<int4> ell;
     DevBuf<int64_t> loc_off, wofs, iters, ctrl;
     DevBuf<float> crho, lo, hi, invN, X, XS, LAM, BB, ash, W;
@@ -726,6 +799,16 @@ void set_chunks(ldopf_batch& h, int32_t rows_per_chunk, int32_t blocks_per_tile)
     const int32_t nch = int32_t(h.chunk_off_h.size()) - 1;
     h.grid = std::max(1, std::min(nch, blocks_per_tile));
     h.chunk_off.upload(h.chunk_off_h, h.stream, "upload chunks");
+    // within a chunk the shared-operator subsystems come first: a block
+    // then switches class once per chunk (a switch to the per-scenario
+    // class costs a barrier)
+    std::vector<LocalMeta> ordered;
+    ordered.reserve(h.meta_h.size());
+    for (int32_t c = 0; c + 1 < int32_t(h.chunk_off_h.size()); ++c)
+        for (int32_t cls : {0, 1})
+            for (int32_t q = h.chunk_off_h[c]; q < h.chunk_off_h[c + 1]; ++q)
+                if (h.meta_h[q].cls == cls) ordered.push_back(h.meta_h[q]);
+    h.meta.upload(ordered, h.stream, "upload subsystems");
     h.part.alloc(size_t(h.grid) * 5 * h.Bp, "residual partials");
     drop_graph(h);
 }
@@ -961,6 +1044,7 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             if (int64_t(L.n) * Bp >= (int64_t(1) << 31)) fail(LDOPF_UNSUPPORTED, "n x padded scenarios exceeds 2^31");
             h->BB.alloc(size_t(nloc) * Bp, "scenario bbar");
             h->W.alloc(size_t(std::max<int64_t>(wrows, 1)) * Bp, "scenario operators");
+            h->w_words = wrows * Bp;
             h->cls.upload(cls, s, "upload classes");
             h->vK.upload(vK, s, "upload classes");
             vbrow_d.upload(vbrow, s, "upload classes");
@@ -1056,7 +1140,7 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             std::vector<LocalMeta> meta(S);
             for (int64_t i = 0; i < S; ++i)
                 meta[i] = LocalMeta{L.ns[i], cls[i], vK[i], vmode[i], L.loc_off[i], cls[i] ? wofs[i] : ash_off_s[i]};
-            h->meta.upload(meta, s, "upload subsystems");
+            h->meta_h = std::move(meta);
 
             // consensus structure: copies of each variable, global data in FP32
             std::vector<int32_t> g32(nloc), var_off(L.n + 1, 0), var_copy(nloc);
@@ -1215,7 +1299,7 @@ int ldopf_batch_get_sizes(const ldopf_batch* h, ldopf_batch_sizes* o) {
         o->n_scen_padded = h->Bp;
         o->n_mfma_subsystems = h->n_mf;
         o->n_vector_subsystems = h->n_vec;
-        o->scenario_operator_words = int64_t(h->W.count);
+        o->scenario_operator_words = h->w_words;
         o->shared_operator_words = int64_t(h->ash.count);
         o->rows_per_chunk = h->rows_per_chunk;
         o->blocks_per_tile = h->grid;
