@@ -109,6 +109,24 @@ typedef enum ldopf_rho_update {
     LDOPF_RHO_BALANCE = 1
 } ldopf_rho_update;
 
+typedef enum ldopf_sweep_path {
+    /* the persistent sweep when its workgroups (one per CU) hold the
+     * problem's operators and state in LDS, else the streamed sweep */
+    LDOPF_PATH_AUTO = 0,
+    /* the persistent sweep only: one cooperative launch per solve, operators
+     * and state in LDS for the whole solve; LDOPF_UNSUPPORTED if they do not
+     * fit */
+    LDOPF_PATH_PERSISTENT = 1,
+    /* the streamed sweep: the same steps of Algorithm 1 with the operators
+     * and state in HBM, three launches per sweep (global update; local and
+     * dual update with the residual sums of each block; the sums in a fixed
+     * order and the test), captured in HIP graphs and replayed by the host
+     * until the test holds. FP64 only, literal residual form and fixed rho;
+     * not for ldopf_solve_noalloc, ldopf_solve_many or the server (those
+     * calls return LDOPF_UNSUPPORTED for such a problem) */
+    LDOPF_PATH_STREAMED = 2
+} ldopf_sweep_path;
+
 /*
  * Network data (nomenclature table of Section II). Structure of arrays,
  * caller-owned, copied by ldopf_create. Per-phase arrays are [count x 3]
@@ -171,7 +189,8 @@ typedef struct ldopf_options {
     int32_t rho_update;      /* ldopf_rho_update; default LDOPF_RHO_FIXED */
     int32_t rho_period;      /* residual balancing: sweeps between evaluations of the rule (>= 4); default 100 */
     int32_t rho_max_changes; /* residual balancing: changes at most (0..1024); default 16 */
-    int32_t reserved[2];     /* must be zero */
+    int32_t sweep_path;      /* ldopf_sweep_path; default LDOPF_PATH_AUTO */
+    int32_t reserved;        /* must be zero */
     double rho_mu;           /* residual balancing: imbalance that triggers a change (> 1); default 10 */
     double rho_tau;          /* residual balancing: factor of a change (> 1); default 2 */
 } ldopf_options;
@@ -189,6 +208,9 @@ typedef struct ldopf_sizes {
     int64_t lds_bytes;  /* LDS per workgroup of the sweep */
     int64_t sync_bytes; /* device bytes of the sweep's exchange words, residual sums and status
                            (what ldopf_solve_noalloc takes from its static array) */
+    int32_t sweep_path; /* the path the problem runs on: LDOPF_PATH_PERSISTENT or LDOPF_PATH_STREAMED
+                           (n_parts, lds_bytes and sync_bytes are 0 on the streamed path) */
+    int32_t reserved;
 } ldopf_sizes;
 
 typedef struct ldopf_status {

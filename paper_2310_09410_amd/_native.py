@@ -31,6 +31,9 @@ LDOPF_RESIDUAL_PAPER = 0
 LDOPF_RESIDUAL_AGGREGATED = 1
 LDOPF_RHO_FIXED = 0
 LDOPF_RHO_BALANCE = 1
+LDOPF_PATH_AUTO = 0
+LDOPF_PATH_PERSISTENT = 1
+LDOPF_PATH_STREAMED = 2
 
 _d = C.POINTER(C.c_double)
 _i32 = C.POINTER(C.c_int32)
@@ -59,7 +62,7 @@ class ldopf_options(C.Structure):
         ("precision", C.c_int32), ("residual_form", C.c_int32), ("check_termination", C.c_int32),
         ("history", C.c_int32), ("rows_per_part", C.c_int32), ("block_threads", C.c_int32),
         ("profile", C.c_int32), ("rho_update", C.c_int32), ("rho_period", C.c_int32),
-        ("rho_max_changes", C.c_int32), ("reserved", C.c_int32 * 2), ("rho_mu", C.c_double),
+        ("rho_max_changes", C.c_int32), ("sweep_path", C.c_int32), ("reserved", C.c_int32), ("rho_mu", C.c_double),
         ("rho_tau", C.c_double),
     ]
 
@@ -69,7 +72,7 @@ class ldopf_sizes(C.Structure):
         ("n", C.c_int64), ("n_sub", C.c_int64), ("n_local", C.c_int64), ("sum_m", C.c_int64),
         ("op_words", C.c_int64), ("rank_words", C.c_int64), ("max_n", C.c_int32), ("max_m", C.c_int32),
         ("n_parts", C.c_int32), ("block_threads", C.c_int32), ("lds_bytes", C.c_int64),
-        ("sync_bytes", C.c_int64),
+        ("sync_bytes", C.c_int64), ("sweep_path", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

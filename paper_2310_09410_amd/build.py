@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libldopf.so")
 ARCH = "gfx950"
 
-SOURCES = ["assemble.cpp", "plan.cpp", "api.cpp", "serve.cpp", "device.hip", "batch.hip"]
+SOURCES = ["assemble.cpp", "plan.cpp", "api.cpp", "serve.cpp", "device.hip", "batch.hip", "stream.hip"]
 
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 arithmetic.
 HIP_FLAGS = [

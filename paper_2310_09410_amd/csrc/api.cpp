@@ -49,8 +49,9 @@ void check_options(const ldopf_options& o) {
     if (o.rows_per_part < 0) fail(LDOPF_INVALID_ARGUMENT, "rows_per_part must be >= 0");
     if (o.block_threads != 0 && (o.block_threads < 128 || o.block_threads > 1024 || o.block_threads % 64))
         fail(LDOPF_INVALID_ARGUMENT, "block_threads must be 0 or a multiple of 64 in [128, 1024]");
-    for (int r : o.reserved)
-        if (r != 0) fail(LDOPF_INVALID_ARGUMENT, "reserved option fields must be zero");
+    if (o.sweep_path != LDOPF_PATH_AUTO && o.sweep_path != LDOPF_PATH_PERSISTENT && o.sweep_path != LDOPF_PATH_STREAMED)
+        fail(LDOPF_INVALID_ARGUMENT, "unknown sweep_path");
+    if (o.reserved != 0) fail(LDOPF_INVALID_ARGUMENT, "reserved option fields must be zero");
 }
 
 void check_batch_options(const ldopf_options& o) {
@@ -75,6 +76,23 @@ void init_state(ldopf_problem& h) {
     hip_check(hipStreamSynchronize(h.stream), "initial state");
     h.have_x = false;
     h.hist_len = 0;
+}
+
+// Global data (cost, bounds, copy counts) and the state buffers, for both
+// sweep paths.
+void c_upload_globals(ldopf_problem& h) {
+    const ConsensusLP& lp = h.lp;
+    hipStream_t s = h.stream;
+    std::vector<double> cnt(lp.n, 0.0);
+    for (int64_t g : lp.gidx) cnt[g] += 1.0;
+    h.c.upload(lp.c, s, "upload c");
+    h.lo.upload(lp.lo, s, "upload lo");
+    h.hi.upload(lp.hi, s, "upload hi");
+    h.cnt.upload(cnt, s, "upload counts");
+    h.xs.alloc(lp.gidx.size(), "x_s");
+    h.lam.alloc(lp.gidx.size(), "lambda");
+    h.x.alloc(lp.n, "x");
+    h.st.alloc(1, "status");
 }
 
 // Everything after the host LP exists: device precompute, plan, buffers.
@@ -153,15 +171,37 @@ void build_device(ldopf_problem& h) {
     h.A.release();
     h.b.release();
 
-    h.plan = make_plan(lp, h.rank, h.fp32, h.opts.rows_per_part, h.opts.block_threads, cus, lds_optin);
+    // the persistent sweep if the problem fits it, else (or on request) the
+    // streamed sweep, which takes FP64, the literal residual form and fixed rho
+    const int32_t path = h.opts.sweep_path;
+    const bool stream_ok = !h.fp32 && h.opts.residual_form == LDOPF_RESIDUAL_PAPER && h.opts.rho_update == LDOPF_RHO_FIXED;
+    auto streamed = [&] {
+        c_upload_globals(h);
+        stream_prepare(h);
+        init_state(h);
+    };
+    if (path == LDOPF_PATH_STREAMED) {
+        if (!stream_ok)
+            fail(LDOPF_UNSUPPORTED, "the streamed sweep runs in FP64 with the literal residual form and fixed rho");
+        streamed();
+        return;
+    }
+    try {
+        h.plan = make_plan(lp, h.rank, h.fp32, h.opts.rows_per_part, h.opts.block_threads, cus, lds_optin);
+        const Plan& pl = h.plan;
+        if (pl.n_parts > kMaxParts) fail(LDOPF_UNSUPPORTED, "more than " + std::to_string(kMaxParts) + " sweep workgroups");
+        hip_check(prepare_sweep(h.fp32, size_t(pl.lds_bytes)), "sweep LDS attribute");
+        int per_cu = 0;
+        hip_check(sweep_occupancy(h.fp32, pl.block_threads, size_t(pl.lds_bytes), &per_cu), "sweep occupancy");
+        if (int64_t(per_cu) * cus < pl.n_parts)
+            fail(LDOPF_UNSUPPORTED, "the sweep's " + std::to_string(pl.n_parts) + " workgroups cannot be co-resident (" +
+                                        std::to_string(per_cu) + " per CU, " + std::to_string(cus) + " CUs)");
+    } catch (const Error& e) {
+        if (e.code != LDOPF_UNSUPPORTED || path != LDOPF_PATH_AUTO || !stream_ok) throw;
+        streamed();
+        return;
+    }
     const Plan& pl = h.plan;
-    if (pl.n_parts > kMaxParts) fail(LDOPF_UNSUPPORTED, "more than " + std::to_string(kMaxParts) + " sweep workgroups");
-    hip_check(prepare_sweep(h.fp32, size_t(pl.lds_bytes)), "sweep LDS attribute");
-    int per_cu = 0;
-    hip_check(sweep_occupancy(h.fp32, pl.block_threads, size_t(pl.lds_bytes), &per_cu), "sweep occupancy");
-    if (int64_t(per_cu) * cus < pl.n_parts)
-        fail(LDOPF_UNSUPPORTED, "the sweep's " + std::to_string(pl.n_parts) + " workgroups cannot be co-resident (" +
-                                    std::to_string(per_cu) + " per CU, " + std::to_string(cus) + " CUs)");
 
     h.parts.upload(pl.parts, s, "upload plan");
     h.subs.upload(pl.subs, s, "upload plan");
@@ -177,19 +217,10 @@ void build_device(ldopf_problem& h) {
     h.var_copy_rows.upload(pl.var_copy_rows, s, "upload plan");
     h.tk_sub.upload(pl.tk_sub, s, "upload plan");
 
-    std::vector<double> cnt(lp.n, 0.0);
-    for (int64_t g : lp.gidx) cnt[g] += 1.0;
-    h.c.upload(lp.c, s, "upload c");
-    h.lo.upload(lp.lo, s, "upload lo");
-    h.hi.upload(lp.hi, s, "upload hi");
-    h.cnt.upload(cnt, s, "upload counts");
-    h.xs.alloc(lp.gidx.size(), "x_s");
-    h.lam.alloc(lp.gidx.size(), "lambda");
-    h.x.alloc(lp.n, "x");
+    c_upload_globals(h);
     h.bpart.alloc(size_t(2) * std::max(pl.n_slots, 1) * (h.fp32 ? 4 : 8), "boundary slots");
     h.rpart.alloc(size_t(kRing) * pl.n_parts * 8, "residual slots");
     h.gpart.alloc(size_t(kRing) * 8 * kGroup, "residual group slots");
-    h.st.alloc(1, "status");
     h.rholog.alloc(size_t(2) * kMaxRhoChanges, "rho log");
     h.prof.alloc(size_t(8) * std::max(pl.n_parts, 1), "phase times");
     init_state(h);
@@ -317,6 +348,23 @@ size_t problem_sync_bytes(const ldopf_problem& h) {
 
 void problem_launch(ldopf_problem& h, const SyncWords* sw, bool cooperative) {
     if (h.in_flight) fail(LDOPF_INVALID_ARGUMENT, "a solve is already in flight on this handle");
+    if (h.streamed) {
+        // the whole solve runs here (the host replays the sweep's graph until
+        // the test holds); the status is then read like the persistent one's
+        if (sw) fail(LDOPF_UNSUPPORTED, "the streamed sweep allocates its own words (no allocation-free solve)");
+        if (h.opts.residual_form != LDOPF_RESIDUAL_PAPER || h.opts.rho_update != LDOPF_RHO_FIXED || h.opts.profile)
+            fail(LDOPF_UNSUPPORTED, "the streamed sweep takes the literal residual form, fixed rho and no profile");
+        const int64_t want = h.opts.history ? std::min<int64_t>(std::max<int64_t>(h.opts.max_iter, 1), int64_t(1) << 22) : 1;
+        if (int64_t(h.hist.count) < want * 4) h.hist.alloc(size_t(want) * 4, "history");
+        hip_check(hipEventRecord(h.ev0, h.stream), "event");
+        stream_solve(h);
+        hip_check(hipEventRecord(h.ev1, h.stream), "event");
+        hip_check(hipMemcpyAsync(h.last_pinned, h.st.p, sizeof(SweepStatus), hipMemcpyDeviceToHost, h.stream),
+                  "download status");
+        hip_check(hipEventRecord(h.done, h.stream), "event");
+        h.in_flight = true;
+        return;
+    }
     if (!sw) {
         const int64_t want = h.opts.history ? std::min<int64_t>(std::max<int64_t>(h.opts.max_iter, 1), int64_t(1) << 22) : 1;
         if (int64_t(h.hist.count) < want * 4) h.hist.alloc(size_t(want) * 4, "history");
@@ -573,7 +621,8 @@ int ldopf_get_sizes(const ldopf_problem* h, ldopf_sizes* o) {
         o->n_parts = h->plan.n_parts;
         o->block_threads = h->plan.block_threads;
         o->lds_bytes = h->plan.lds_bytes;
-        o->sync_bytes = int64_t(problem_sync_bytes(*h));
+        o->sync_bytes = h->streamed ? 0 : int64_t(problem_sync_bytes(*h));
+        o->sweep_path = h->streamed ? LDOPF_PATH_STREAMED : LDOPF_PATH_PERSISTENT;
     });
 }
 
@@ -583,8 +632,8 @@ int ldopf_set_options(ldopf_problem* h, const ldopf_options* opts) {
         need(opts, "opts");
         check_options(*opts);
         if (opts->precision != h->opts.precision || opts->rows_per_part != h->opts.rows_per_part ||
-            opts->block_threads != h->opts.block_threads)
-            fail(LDOPF_INVALID_ARGUMENT, "precision and tuning fields are fixed at creation");
+            opts->block_threads != h->opts.block_threads || opts->sweep_path != h->opts.sweep_path)
+            fail(LDOPF_INVALID_ARGUMENT, "precision, sweep path and tuning fields are fixed at creation");
         h->opts = *opts;
     });
 }
@@ -698,6 +747,7 @@ int ldopf_solve_many(ldopf_problem* const* hs, int32_t count, ldopf_status* stat
             for (int32_t j = 0; j < i; ++j)
                 if (v[j] == v[i]) fail(LDOPF_INVALID_ARGUMENT, "a problem appears twice");
             if (v[i]->in_flight) fail(LDOPF_INVALID_ARGUMENT, "a solve is already in flight on a problem");
+            if (v[i]->streamed) fail(LDOPF_UNSUPPORTED, "a problem on the streamed sweep cannot share a launch");
             if (v[i]->fp32 != v[0]->fp32 || v[i]->opts.residual_form != v[0]->opts.residual_form ||
                 v[i]->opts.profile != v[0]->opts.profile || v[i]->device != v[0]->device)
                 fail(LDOPF_INVALID_ARGUMENT, "the problems must share precision, residual form, profiling and device");

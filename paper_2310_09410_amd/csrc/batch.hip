@@ -537,6 +537,20 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
 // ticket per tile) adds the slices in order and runs the termination test,
 // the masks; the last tile to finish advances the sweep counter and decides
 // whether the batch is done. The order of every sum is fixed.
+// Words read by other blocks of the same launch (the slice sums) go through
+// the device's coherence point (agent-scope relaxed atomics); a block makes
+// them visible before it takes its ticket by waiting for its own stores to
+// complete (s_waitcnt 0) instead of a device-scope release fence, which would
+// write back the whole L2 of its XCD.
+__device__ inline void st_dev(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_dev(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 __global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
     if (a.ctrl[1]) return;
     __shared__ double red[16][5][64];
@@ -573,23 +587,21 @@ __global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
         for (int q = 0; q < 5; ++q) {
             double t = 0.0;
             for (int w = 0; w < 16; ++w) t += red[w][q][lane];
-            slice[(rb * 5 + q) * kTile + lane] = t;
+            st_dev(slice + (rb * 5 + q) * kTile + lane, t);
         }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last = atomicAdd(&a.tick[tile], 1) == kRedBlocks - 1;
-    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&a.tick[tile], 1) == kRedBlocks - 1;
     __syncthreads();
     if (!last) return;
-    __threadfence();
     const int64_t t_now = a.ctrl[0] + 1;
     if (wv == 0) {
         double d[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             double t = 0.0;
-            for (int b2 = 0; b2 < kRedBlocks; ++b2) t += slice[(b2 * 5 + q) * kTile + lane];
+            for (int b2 = 0; b2 < kRedBlocks; ++b2) t += ld_dev(slice + (b2 * 5 + q) * kTile + lane);
             d[q] = t;
         }
         int still = 0;
@@ -618,10 +630,9 @@ __global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        __builtin_amdgcn_s_waitcnt(0);
         const unsigned long long prev = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[3]), 1ull);
         if (prev == unsigned(a.Bp / kTile) - 1) {
-            __threadfence();
             const long long left = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), 0ull);
             a.ctrl[0] = t_now;
             a.ctrl[2] = 0;

@@ -55,16 +55,27 @@ struct ldopf_problem {
     DevBuf<uint8_t> var_writer;
     DevBuf<unsigned char> bpart;
     DevBuf<SweepStatus> st;
+    // streamed sweep (a problem too large for the persistent sweep's LDS):
+    // per-subsystem words, copies as 32-bit indices, the copies of each
+    // variable (CSR), the blocks' residual rows, control words, the graph
+    bool streamed = false;
+    int32_t s_nq = 1;
+    DevBuf<int64_t> s_meta, s_ctrl;
+    DevBuf<int32_t> s_gidx, s_var_off, s_var_copy;
+    DevBuf<double> s_part;
+    hipGraph_t s_graph = nullptr;
+    hipGraphExec_t s_exec = nullptr;
 
     // every device buffer allocated and released in order on `s` (the
     // serving runtime's slot streams, which outlive their problems)
     void use_stream_ordered_memory(hipStream_t s) {
         for (DevBuf<double>* q : {&A, &b, &basis, &abar, &bbar, &c, &lo, &hi, &cnt, &xs, &lam, &x, &hist, &rpart, &gpart,
-                                  &prof, &rholog, &bagg})
+                                  &prof, &rholog, &bagg, &s_part})
             q->ordered = s;
-        for (DevBuf<int32_t>* q : {&ns, &ms, &rank_d, &flags, &row_canon, &var_gid, &var_slot, &var_slot_lo, &var_slot_hi})
+        for (DevBuf<int32_t>* q : {&ns, &ms, &rank_d, &flags, &row_canon, &var_gid, &var_slot, &var_slot_lo, &var_slot_hi,
+                                   &s_gidx, &s_var_off, &s_var_copy})
             q->ordered = s;
-        for (DevBuf<int64_t>* q : {&a_off, &row_off, &loc_off, &basis_off}) q->ordered = s;
+        for (DevBuf<int64_t>* q : {&a_off, &row_off, &loc_off, &basis_off, &s_meta, &s_ctrl}) q->ordered = s;
         for (DevBuf<uint16_t>* q : {&row_lvar, &row_sub, &var_copy_off, &var_copy_rows, &tk_sub}) q->ordered = s;
         parts.ordered = s;
         subs.ordered = s;
@@ -75,6 +86,8 @@ struct ldopf_problem {
 
     ~ldopf_problem() {
         if (stream) (void)hipStreamSynchronize(stream);
+        if (s_exec) (void)hipGraphExecDestroy(s_exec);
+        if (s_graph) (void)hipGraphDestroy(s_graph);
         if (own_pinned && last_pinned) (void)hipHostFree(last_pinned);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -111,6 +124,11 @@ void problem_launch(ldopf_problem& h, const SyncWords* sw = nullptr, bool cooper
 bool problem_ready(const ldopf_problem& h);
 // Wait for the enqueued solve, read its status; returns the ldopf_code.
 int problem_finish(ldopf_problem& h, ldopf_status* status);
+// Streamed sweep: device tables of a problem whose precompute is done
+// (switches the handle to that path), and one whole solve, enqueued and
+// waited for on the handle's stream (throws).
+void stream_prepare(ldopf_problem& h);
+void stream_solve(ldopf_problem& h);
 // Device bytes a problem allocates at its peak (creation plus one solve).
 int64_t problem_device_bytes(const ConsensusLP& lp, const ldopf_options& opts);
 // Workgroups of its sweep, planned on the host assuming full row rank.

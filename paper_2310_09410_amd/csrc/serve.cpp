@@ -282,6 +282,9 @@ int ldopf_server_submit(ldopf_server* srv, const ldopf_network* net, const ldopf
         ldopf_default_options(&o);
         if (opts) o = *opts;
         check_options(o);
+        if (o.sweep_path == LDOPF_PATH_STREAMED)
+            fail(LDOPF_UNSUPPORTED, "served requests run on the persistent sweep (admitted by compute units)");
+        o.sweep_path = LDOPF_PATH_PERSISTENT;  // a request too large for it fails at admission
         o.history = 0;  // results only; no per-sweep history on the server
         auto r = std::make_unique<Request>();
         r->lp = assemble_network(*net);

@@ -1,0 +1,345 @@
+// Streamed sweep: the path for problems whose operators and state do not fit
+// the LDS of one workgroup per CU (the persistent sweep's requirement).
+//
+// The same sweep as the persistent kernel (Algorithm 1: global update of
+// closed_1 in its derived form, local update of closed_2 in rank form, dual
+// update ADMM-3, the residual sums and the test of Section III-C), with every
+// operand in HBM and one launch per step: the global update (a thread per
+// variable, its copies from a CSR list), the local and dual update (a wave
+// per subsystem, a lane per row: t_k = sum_j W_kj v_j by a butterfly sum over
+// the wave, then y_j = bbar_j + v_j - sum_k W_kj t_k in mode 1 or bbar_j +
+// sum_k W_kj t_k in mode 0, with W the K_s rows of the precomputed basis that
+// span the smaller of the row space and its complement), and the residual
+// sums over the blocks' partial rows with the test, in a fixed order. A
+// launch after the sweep that passed the test returns at once, so C sweeps
+// are captured in one HIP graph and the host replays it until the test
+// holds. FP64 throughout; the returned state is that of the sweep that
+// passed the test.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "problem.h"
+
+namespace ldopf {
+
+namespace {
+
+constexpr int kSWaves = 8;    // waves per block of the local update
+constexpr int kSBlocks = 512; // blocks of the local update: rows of partial sums
+constexpr int kSGraph = 32;   // sweeps per captured graph
+
+struct StreamArgs {
+    int64_t S, n, nloc;
+    const int64_t* meta;  // per subsystem: n_s | K_s << 16 | mode << 32, first copy, offset of W in the basis
+    const int32_t* gidx;
+    const int32_t* var_off;
+    const int32_t* var_copy;
+    const double* basis;
+    const double* bbar;
+    const double* c;
+    const double* lo;
+    const double* hi;
+    const double* cnt;
+    double* x;
+    double* xs;
+    double* lam;
+    double* part;  // [kSBlocks][5]
+    int64_t* ctrl; // [0] sweeps done, [1] stopped
+    double* hist;
+    int64_t hist_cap;
+    SweepStatus* st;
+    double rho, eps_rel, eps_abs;
+    int64_t max_iter;
+    int32_t check;
+};
+
+__device__ inline double wave_sum(double v) {
+    // xor butterfly: every lane ends with the same bits
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__global__ void stream_init_kernel(StreamArgs a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    a.ctrl[0] = 0;
+    a.ctrl[1] = a.max_iter == 0 ? 1 : 0;
+    SweepStatus* st = a.st;
+    st->iters = 0;
+    st->computed = 0;
+    st->converged = 0;
+    st->flags = 0;
+    st->pres = st->dres = st->eps_p = st->eps_d = 0.0;
+    st->rho = a.rho;
+    st->rho_changes = 0;
+}
+
+// closed_1: x_i = clip((sum_c x_s,c - (c_i + sum_c lambda_c) / rho) / N_i) over
+// the copies c of variable i, in copy order (a NaN passes the clip).
+__global__ __launch_bounds__(256) void stream_global_kernel(StreamArgs a) {
+    if (a.ctrl[1]) return;
+    const int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (v >= a.n) return;
+    double sx = 0.0, sl = 0.0;
+    for (int q = a.var_off[v]; q < a.var_off[v + 1]; ++q) {
+        const int c = a.var_copy[q];
+        sx += a.xs[c];
+        sl += a.lam[c];
+    }
+    const double xh = (sx - (a.c[v] + sl) / a.rho) / a.cnt[v];
+    const double lo = a.lo[v], hi = a.hi[v];
+    a.x[v] = xh < lo ? lo : (xh > hi ? hi : xh);
+}
+
+// closed_2, ADMM-3 and the residual sums; NQ rows per lane (n_s <= 64 NQ).
+template <int NQ>
+__global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a) {
+    if (a.ctrl[1]) return;
+    __shared__ double red[kSWaves][5];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double rho = a.rho, irho = 1.0 / a.rho;
+    double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t s = int64_t(blockIdx.x) * kSWaves + wv; s < a.S; s += int64_t(gridDim.x) * kSWaves) {
+        const int64_t m0 = a.meta[3 * s];
+        const int n = int(m0 & 0xffff), K = int((m0 >> 16) & 0xffff), mode = int((m0 >> 32) & 1);
+        const int64_t row0 = a.meta[3 * s + 1];
+        const double* W = a.basis + a.meta[3 * s + 2];
+        double z[NQ], l[NQ], xo[NQ], v[NQ], acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = lane + 64 * q;
+            z[q] = l[q] = xo[q] = v[q] = acc[q] = 0.0;
+            if (j < n) {
+                const int64_t c = row0 + j;
+                z[q] = a.x[a.gidx[c]];
+                l[q] = a.lam[c];
+                xo[q] = a.xs[c];
+                v[q] = z[q] + l[q] * irho;
+            }
+        }
+        for (int k = 0; k < K; ++k) {
+            double w[NQ];
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int j = lane + 64 * q;
+                w[q] = j < n ? W[int64_t(k) * n + j] : 0.0;
+                t += w[q] * v[q];
+            }
+            t = wave_sum(t);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += w[q] * t;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = lane + 64 * q;
+            if (j < n) {
+                const int64_t c = row0 + j;
+                const double y = a.bbar[c] + (mode ? v[q] - acc[q] : acc[q]);
+                const double l1 = l[q] + rho * (z[q] - y);
+                a.xs[c] = y;
+                a.lam[c] = l1;
+                const double dz = z[q] - y, dx = y - xo[q];
+                p[0] += dz * dz;
+                p[1] += dx * dx;
+                p[2] += z[q] * z[q];
+                p[3] += y * y;
+                p[4] += l1 * l1;
+            }
+        }
+    }
+    // the wave's sums (butterfly), then the waves in order
+#pragma unroll
+    for (int q = 0; q < 5; ++q) p[q] = wave_sum(p[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) red[wv][q] = p[q];
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double t = 0.0;
+        for (int w = 0; w < kSWaves; ++w) t += red[w][threadIdx.x];
+        a.part[int64_t(blockIdx.x) * 5 + threadIdx.x] = t;
+    }
+}
+
+// The partial rows in a fixed order (thread r takes row r, butterfly over
+// each wave, then the waves in order), the test, history and status.
+__global__ __launch_bounds__(1024) void stream_test_kernel(StreamArgs a, int rows) {
+    if (a.ctrl[1]) return;
+    __shared__ double red[16][5];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = threadIdx.x; r < rows; r += 1024)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) p[q] += a.part[int64_t(r) * 5 + q];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) p[q] = wave_sum(p[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) red[wv][q] = p[q];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double d[5];
+    for (int q = 0; q < 5; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += red[w][q];
+        d[q] = t;
+    }
+    const int64_t k = a.ctrl[0] + 1;
+    const double sq = sqrt(double(a.nloc));
+    const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
+    const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
+    const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
+    if (k <= a.hist_cap) {
+        double* h = a.hist + (k - 1) * 4;
+        h[0] = pres;
+        h[1] = dres;
+        h[2] = eps_p;
+        h[3] = eps_d;
+    }
+    const bool conv = pres <= eps_p && dres <= eps_d;
+    const bool bad = !isfinite(d[0] + d[1] + d[2] + d[3] + d[4]);
+    SweepStatus* st = a.st;
+    st->iters = k;
+    st->computed = k;
+    st->converged = conv ? 1 : 0;
+    st->pres = pres;
+    st->dres = dres;
+    st->eps_p = eps_p;
+    st->eps_d = eps_d;
+    if (bad) st->flags |= 2;
+    a.ctrl[0] = k;
+    a.ctrl[1] = (bad || (a.check && conv) || k >= a.max_iter) ? 1 : 0;
+}
+
+StreamArgs stream_args(ldopf_problem& h) {
+    StreamArgs a{};
+    a.S = h.lp.S;
+    a.n = h.lp.n;
+    a.nloc = int64_t(h.lp.gidx.size());
+    a.meta = h.s_meta.p;
+    a.gidx = h.s_gidx.p;
+    a.var_off = h.s_var_off.p;
+    a.var_copy = h.s_var_copy.p;
+    a.basis = h.basis.p;
+    a.bbar = h.bbar.p;
+    a.c = h.c.p;
+    a.lo = h.lo.p;
+    a.hi = h.hi.p;
+    a.cnt = h.cnt.p;
+    a.x = h.x.p;
+    a.xs = h.xs.p;
+    a.lam = h.lam.p;
+    a.part = h.s_part.p;
+    a.ctrl = h.s_ctrl.p;
+    a.hist = h.hist.p;
+    a.hist_cap = h.opts.history ? int64_t(h.hist.count / 4) : 0;
+    a.st = h.st.p;
+    a.rho = h.opts.rho;
+    a.eps_rel = h.opts.eps_rel;
+    a.eps_abs = h.opts.eps_abs;
+    a.max_iter = h.opts.max_iter;
+    a.check = h.opts.check_termination;
+    return a;
+}
+
+const void* local_kernel(int nq) {
+    switch (nq) {
+        case 1: return reinterpret_cast<const void*>(&stream_local_kernel<1>);
+        case 4: return reinterpret_cast<const void*>(&stream_local_kernel<4>);
+        default: return reinterpret_cast<const void*>(&stream_local_kernel<16>);
+    }
+}
+
+void drop_stream_graph(ldopf_problem& h) {
+    if (h.s_exec) {
+        (void)hipGraphExecDestroy(h.s_exec);
+        h.s_exec = nullptr;
+    }
+    if (h.s_graph) {
+        (void)hipGraphDestroy(h.s_graph);
+        h.s_graph = nullptr;
+    }
+}
+
+}  // namespace
+
+void stream_prepare(ldopf_problem& h) {
+    const ConsensusLP& lp = h.lp;
+    hipStream_t s = h.stream;
+    const int64_t S = lp.S, nloc = int64_t(lp.gidx.size());
+    if (nloc >= (int64_t(1) << 31) || lp.n >= (int64_t(1) << 31))
+        fail(LDOPF_UNSUPPORTED, "the streamed sweep indexes copies and variables with 32-bit integers");
+    std::vector<int64_t> meta(size_t(3) * S);
+    int64_t off = 0, rank_words = 0;
+    int32_t max_n = 1;
+    for (int64_t i = 0; i < S; ++i) {
+        const int64_t n = lp.ns[i], r = h.rank[i];
+        const int64_t mode = r <= n - r ? 1 : 0, K = std::min(r, n - r);
+        meta[3 * i] = n | (K << 16) | (mode << 32);
+        meta[3 * i + 1] = lp.loc_off[i];
+        meta[3 * i + 2] = off + (mode ? 0 : r) * n;  // the K rows of the basis that the rank form uses
+        off += n * n;
+        rank_words += n * K;
+        max_n = std::max<int32_t>(max_n, int32_t(n));
+    }
+    std::vector<int32_t> g32(nloc), var_off(lp.n + 1, 0), var_copy(nloc);
+    for (int64_t c = 0; c < nloc; ++c) {
+        g32[c] = int32_t(lp.gidx[c]);
+        var_off[lp.gidx[c] + 1]++;
+    }
+    for (int64_t v = 0; v < lp.n; ++v) var_off[v + 1] += var_off[v];
+    std::vector<int32_t> fill(var_off.begin(), var_off.end() - 1);
+    for (int64_t c = 0; c < nloc; ++c) var_copy[fill[lp.gidx[c]]++] = int32_t(c);
+    h.s_meta.upload(meta, s, "upload streamed plan");
+    h.s_gidx.upload(g32, s, "upload streamed plan");
+    h.s_var_off.upload(var_off, s, "upload streamed plan");
+    h.s_var_copy.upload(var_copy, s, "upload streamed plan");
+    h.s_part.alloc(size_t(kSBlocks) * 5, "streamed residual rows");
+    h.s_ctrl.alloc(2, "streamed control");
+    h.s_nq = max_n <= 64 ? 1 : (max_n <= 256 ? 4 : 16);
+    h.streamed = true;
+    h.plan = Plan{};
+    h.plan.rank_words = rank_words;
+    h.plan.block_threads = 64 * kSWaves;
+    drop_stream_graph(h);
+}
+
+void stream_solve(ldopf_problem& h) {
+    // the graph holds the kernel arguments (options, buffers): capture anew
+    // for every solve, which also follows option changes
+    drop_stream_graph(h);
+    const StreamArgs a = stream_args(h);
+    hipStream_t s = h.stream;
+    hipLaunchKernelGGL(stream_init_kernel, dim3(1), dim3(64), 0, s, a);
+    hip_check(hipGetLastError(), "streamed sweep init");
+    const unsigned gblocks = unsigned((a.n + 255) / 256);
+    const int rows = int(std::min<int64_t>(kSBlocks, std::max<int64_t>(1, (a.S + kSWaves - 1) / kSWaves)));
+    hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
+    for (int i = 0; i < kSGraph; ++i) {
+        hipLaunchKernelGGL(stream_global_kernel, dim3(std::max(gblocks, 1u)), dim3(256), 0, s, a);
+        StreamArgs copy = a;
+        void* args[] = {&copy};
+        (void)hipLaunchKernel(local_kernel(h.s_nq), dim3(rows), dim3(64 * kSWaves), args, 0, s);
+        hipLaunchKernelGGL(stream_test_kernel, dim3(1), dim3(1024), 0, s, a, rows);
+    }
+    hip_check(hipStreamEndCapture(s, &h.s_graph), "graph capture");
+    hip_check(hipGraphInstantiate(&h.s_exec, h.s_graph, nullptr, nullptr, 0), "graph instantiate");
+    int64_t ctrl[2] = {0, 0};
+    for (;;) {
+        const int64_t before = ctrl[0];
+        hip_check(hipGraphLaunch(h.s_exec, s), "graph launch");
+        hip_check(hipMemcpyAsync(ctrl, h.s_ctrl.p, sizeof(ctrl), hipMemcpyDeviceToHost, s), "download control");
+        hip_check(hipStreamSynchronize(s), "streamed sweep");
+        if (ctrl[1]) break;
+        // every sweep of a graph that did not stop advances the count
+        if (ctrl[0] != before + kSGraph) fail(LDOPF_DEVICE_ERROR, "the streamed sweep count did not advance");
+    }
+}
+
+}  // namespace ldopf

@@ -11,8 +11,11 @@ import ctypes as C
 import numpy as np
 
 from . import _native as N
-from ._native import (LDOPF_FP32_MIXED, LDOPF_FP64, LDOPF_NOT_CONVERGED, LDOPF_OK,  # noqa: F401
+from ._native import (LDOPF_BUFFER_TOO_SMALL, LDOPF_DEVICE_ERROR, LDOPF_INCONSISTENT_SUBSYSTEM,  # noqa: F401
+                      LDOPF_INVALID_ARGUMENT, LDOPF_NUMERICAL, LDOPF_OUT_OF_MEMORY, LDOPF_UNSUPPORTED,
+                      LDOPF_FP32_MIXED, LDOPF_FP64, LDOPF_NOT_CONVERGED, LDOPF_OK,
                       LDOPF_REQ_DONE, LDOPF_REQ_FAILED, LDOPF_REQ_QUEUED, LDOPF_REQ_RUNNING,
+                      LDOPF_PATH_AUTO, LDOPF_PATH_PERSISTENT, LDOPF_PATH_STREAMED,
                       LDOPF_RESIDUAL_AGGREGATED, LDOPF_RESIDUAL_PAPER, LDOPF_RHO_BALANCE, LDOPF_RHO_FIXED,
                       ldopf_batch_sizes, ldopf_batch_status,
                       ldopf_options, ldopf_server_stats, ldopf_sizes, ldopf_status)

@@ -114,6 +114,7 @@ def test_default_options():
     o = P.ldopf_default_options()
     assert o.rho == 100.0 and o.eps_rel == 1e-4 and o.max_iter == 1000000
     assert o.precision == 0 and o.residual_form == 0 and o.check_termination == 1
+    assert o.sweep_path == P.ldopf.LDOPF_PATH_AUTO
 
 
 @pytest.mark.parametrize("field,value", [
@@ -125,6 +126,8 @@ def test_default_options():
     ("eps_rel", -1.0),
     ("max_iter", -1),
     ("check_termination", 2),
+    ("sweep_path", 3),
+    ("reserved", 1),
 ])
 def test_options_out_of_range_are_rejected_before_any_device_work(field, value):
     """Option bounds (include/ldopf.h, ldopf_options) are checked on the host
