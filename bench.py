@@ -146,6 +146,48 @@ def run_many(P, make_feeder, stream, n13: int = 64, n123: int = 16) -> dict:
     return out
 
 
+def run_streamed(P, L, make_feeder, net8500, iters_persistent: int, us_persistent: float, stream) -> dict:
+    """The streamed sweep (operators and state in HBM, three launches per
+    sweep replayed as HIP graphs): on the 8500-bus feeder beside the
+    persistent sweep, and on a 12,000-bus feeder (the 8500-bus recipe with
+    more buses), which the persistent sweep cannot hold in FP64 and the
+    automatic choice streams; FP64, each to eps_rel 1e-4."""
+    import dataclasses
+    from synth import SPECS
+    out = {}
+
+    def solve(net, opts):
+        p = P.ldopf_create(net, opts, stream=stream)
+        warm = P.ldopf_default_options(max_iter=64, check_termination=0, sweep_path=opts.sweep_path)
+        keep = P.ldopf_default_options(sweep_path=opts.sweep_path)
+        p.set_options(warm)
+        p.solve()  # warm: kernels loaded, graph path exercised
+        p.reset()
+        p.set_options(keep)
+        t0 = time.perf_counter()
+        st = p.solve()
+        dt = time.perf_counter() - t0
+        s = p.sizes()
+        us = 1e3 * st.sweep_ms / max(1, st.sweeps_computed)
+        rec = {"path": "streamed" if s.sweep_path == L.LDOPF_PATH_STREAMED else "persistent",
+               "iterations_to_tol": st.iterations, "converged": bool(st.converged), "time_to_tol_s": dt,
+               "us_per_sweep": us, "subsystems": s.n_sub, "local_copies": s.n_local,
+               "bytes_per_sweep": algorithmic_bytes_per_sweep(s, 8),
+               "achieved_GBs": algorithmic_bytes_per_sweep(s, 8) / (us * 1e-6) / 1e9, "objective": p.objective()}
+        rec["frac_of_hbm_peak"] = rec["achieved_GBs"] / HBM_PEAK_GBS
+        p.close()
+        return rec
+
+    out["8500"] = solve(net8500, P.ldopf_default_options(sweep_path=L.LDOPF_PATH_STREAMED))
+    out["8500"]["persistent_iterations_to_tol"] = iters_persistent
+    out["8500"]["persistent_us_per_sweep"] = us_persistent
+    big = make_feeder(dataclasses.replace(SPECS["8500"], n_bus=12000), 12000)
+    out["12000"] = solve(big, P.ldopf_default_options())
+    out["12000"]["workload"] = ("12,000-bus synthetic feeder (the 8500-bus recipe, seed 12000), FP64 to eps_rel 1e-4: "
+                                "too large for the LDS-resident sweep, run on the streamed one")
+    return out
+
+
 def _serving_requests(make_feeder, n_req: int, seed: int, id0: int):
     """n_req requests: feeder size uniform over {13, 123, 2500, 8500} buses,
     a fresh feeder seed each (id0 + i), FP32-mixed or FP64 with probability
@@ -324,6 +366,7 @@ def main():
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-rho-balance", action="store_true")
     ap.add_argument("--no-many", action="store_true")
+    ap.add_argument("--no-streamed", action="store_true")
     args = ap.parse_args()
     if args.cpu_baseline_only:
         _cpu_baseline_child(args.cpu_baseline_only, args.cpu_threads)
@@ -469,6 +512,9 @@ def main():
     if not args.no_many:
         rec["feeders_one_launch"] = run_many(P, make_feeder, stream)
         progress(f"feeders in one launch: {rec['feeders_one_launch']['speedup']:.1f}x one by one")
+    if not args.no_streamed:
+        rec["streamed"] = run_streamed(P, L, make_feeder, net, rec["iterations_to_tol"], rec["us_per_sweep"], stream)
+        progress(f"streamed: 12000-bus in {rec['streamed']['12000']['time_to_tol_s']:.1f} s")
     if not args.no_batched:
         rec["batched"] = run_batched(P, L, make_feeder, scenario_factors, stream)
         progress(f"batched: {rec['batched']['solves_per_s']:.2f} solves/s")

@@ -60,8 +60,9 @@ struct ldopf_problem {
     // variable (CSR), the blocks' residual rows, control words, the graph
     bool streamed = false;
     int32_t s_nq = 1;
+    int64_t s_n_groups = 0;
     DevBuf<int64_t> s_meta, s_ctrl;
-    DevBuf<int32_t> s_gidx, s_var_off, s_var_copy;
+    DevBuf<int32_t> s_gidx, s_var_off, s_var_copy, s_groups;
     DevBuf<double> s_part;
     hipGraph_t s_graph = nullptr;
     hipGraphExec_t s_exec = nullptr;
@@ -73,7 +74,7 @@ struct ldopf_problem {
                                   &prof, &rholog, &bagg, &s_part})
             q->ordered = s;
         for (DevBuf<int32_t>* q : {&ns, &ms, &rank_d, &flags, &row_canon, &var_gid, &var_slot, &var_slot_lo, &var_slot_hi,
-                                   &s_gidx, &s_var_off, &s_var_copy})
+                                   &s_gidx, &s_var_off, &s_var_copy, &s_groups})
             q->ordered = s;
         for (DevBuf<int64_t>* q : {&a_off, &row_off, &loc_off, &basis_off, &s_meta, &s_ctrl}) q->ordered = s;
         for (DevBuf<uint16_t>* q : {&row_lvar, &row_sub, &var_copy_off, &var_copy_rows, &tk_sub}) q->ordered = s;

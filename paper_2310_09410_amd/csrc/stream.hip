@@ -31,12 +31,14 @@ namespace ldopf {
 namespace {
 
 constexpr int kSWaves = 8;    // waves per block of the local update
-constexpr int kSBlocks = 512; // blocks of the local update: rows of partial sums
+constexpr int kSBlocks = 1024; // blocks of the local update: rows of partial sums
 constexpr int kSGraph = 32;   // sweeps per captured graph
 
 struct StreamArgs {
     int64_t S, n, nloc;
     const int64_t* meta;  // per subsystem: n_s | K_s << 16 | mode << 32, first copy, offset of W in the basis
+    const int32_t* groups;  // per group of subsystems: lanes each, count, largest K_s, 0, then up to 4 subsystems
+    int64_t n_groups;
     const int32_t* gidx;
     const int32_t* var_off;
     const int32_t* var_copy;
@@ -96,23 +98,40 @@ __global__ __launch_bounds__(256) void stream_global_kernel(StreamArgs a) {
     a.x[v] = xh < lo ? lo : (xh > hi ? hi : xh);
 }
 
-// closed_2, ADMM-3 and the residual sums; NQ rows per lane (n_s <= 64 NQ).
+// closed_2, ADMM-3 and the residual sums. A wave takes one group of
+// subsystems at a time: four of at most 16 variables (16 lanes each), two of
+// at most 32, or one (64 lanes, NQ rows per lane, n_s <= 64 NQ); a lane holds
+// row j of its subsystem, and t_k is a butterfly sum over the subsystem's
+// lanes. Operator rows are loaded kKB at a time (fewer for more rows per
+// lane, so that the batch stays in registers).
 template <int NQ>
 __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a) {
+    constexpr int kKB = NQ >= 16 ? 1 : 2;
     if (a.ctrl[1]) return;
     __shared__ double red[kSWaves][5];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double rho = a.rho, irho = 1.0 / a.rho;
     double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t s = int64_t(blockIdx.x) * kSWaves + wv; s < a.S; s += int64_t(gridDim.x) * kSWaves) {
-        const int64_t m0 = a.meta[3 * s];
-        const int n = int(m0 & 0xffff), K = int((m0 >> 16) & 0xffff), mode = int((m0 >> 32) & 1);
-        const int64_t row0 = a.meta[3 * s + 1];
-        const double* W = a.basis + a.meta[3 * s + 2];
+    for (int64_t g = int64_t(blockIdx.x) * kSWaves + wv; g < a.n_groups; g += int64_t(gridDim.x) * kSWaves) {
+        const int32_t* gr = a.groups + 8 * g;
+        const int G = gr[0], count = gr[1], kmax = gr[2];
+        const int slot = lane / G, jl = lane - slot * G;
+        const int sub = slot < count ? gr[4 + slot] : -1;
+        int n = 0, K = 0, mode = 0;
+        int64_t row0 = 0;
+        const double* W = a.basis;
+        if (sub >= 0) {
+            const int64_t m0 = a.meta[3 * int64_t(sub)];
+            n = int(m0 & 0xffff);
+            K = int((m0 >> 16) & 0xffff);
+            mode = int((m0 >> 32) & 1);
+            row0 = a.meta[3 * int64_t(sub) + 1];
+            W = a.basis + a.meta[3 * int64_t(sub) + 2];
+        }
         double z[NQ], l[NQ], xo[NQ], v[NQ], acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int j = lane + 64 * q;
+            const int j = jl + 64 * q;
             z[q] = l[q] = xo[q] = v[q] = acc[q] = 0.0;
             if (j < n) {
                 const int64_t c = row0 + j;
@@ -122,22 +141,34 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
                 v[q] = z[q] + l[q] * irho;
             }
         }
-        for (int k = 0; k < K; ++k) {
-            double w[NQ];
-            double t = 0.0;
+        // all loads of a batch first, then its butterfly sums side by side
+        for (int k0 = 0; k0 < kmax; k0 += kKB) {
+            double w[kKB][NQ];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int j = lane + 64 * q;
-                w[q] = j < n ? W[int64_t(k) * n + j] : 0.0;
-                t += w[q] * v[q];
+            for (int kb = 0; kb < kKB; ++kb)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int j = jl + 64 * q;
+                    w[kb][q] = (j < n && k0 + kb < K) ? W[int64_t(k0 + kb) * n + j] : 0.0;
+                }
+            double t[kKB];
+#pragma unroll
+            for (int kb = 0; kb < kKB; ++kb) {
+                t[kb] = 0.0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) t[kb] += w[kb][q] * v[q];
             }
-            t = wave_sum(t);
+            for (int m = G >> 1; m >= 1; m >>= 1)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[q] += w[q] * t;
+                for (int kb = 0; kb < kKB; ++kb) t[kb] += __shfl_xor(t[kb], m, 64);
+#pragma unroll
+            for (int kb = 0; kb < kKB; ++kb)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) acc[q] += w[kb][q] * t[kb];
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int j = lane + 64 * q;
+            const int j = jl + 64 * q;
             if (j < n) {
                 const int64_t c = row0 + j;
                 const double y = a.bbar[c] + (mode ? v[q] - acc[q] : acc[q]);
@@ -223,6 +254,8 @@ StreamArgs stream_args(ldopf_problem& h) {
     a.n = h.lp.n;
     a.nloc = int64_t(h.lp.gidx.size());
     a.meta = h.s_meta.p;
+    a.groups = h.s_groups.p;
+    a.n_groups = h.s_n_groups;
     a.gidx = h.s_gidx.p;
     a.var_off = h.s_var_off.p;
     a.var_copy = h.s_var_copy.p;
@@ -296,7 +329,33 @@ void stream_prepare(ldopf_problem& h) {
     for (int64_t v = 0; v < lp.n; ++v) var_off[v + 1] += var_off[v];
     std::vector<int32_t> fill(var_off.begin(), var_off.end() - 1);
     for (int64_t c = 0; c < nloc; ++c) var_copy[fill[lp.gidx[c]]++] = int32_t(c);
+    // groups of subsystems per wave: the largest first (longest chains),
+    // then pairs of at most 32 variables, then fours of at most 16; with any
+    // subsystem above 64 variables, one subsystem per wave throughout
+    std::vector<int32_t> groups;
+    int64_t n_groups = 0;
+    auto add_group = [&](int32_t G, const std::vector<int32_t>& subs) {
+        int32_t kmax = 0;
+        for (int32_t q : subs) kmax = std::max<int32_t>(kmax, int32_t((meta[3 * size_t(q)] >> 16) & 0xffff));
+        groups.insert(groups.end(), {G, int32_t(subs.size()), kmax, 0, -1, -1, -1, -1});
+        for (size_t i = 0; i < subs.size(); ++i) groups[groups.size() - 4 + i] = subs[i];
+        ++n_groups;
+    };
+    std::vector<int32_t> s16, s32, s64;
+    for (int64_t i = 0; i < S; ++i) {
+        const int32_t n = lp.ns[i];
+        if (max_n > 64 || n > 32) s64.push_back(int32_t(i));
+        else if (n > 16) s32.push_back(int32_t(i));
+        else s16.push_back(int32_t(i));
+    }
+    for (int32_t q : s64) add_group(64, {q});
+    for (size_t i = 0; i < s32.size(); i += 2)
+        add_group(32, std::vector<int32_t>(s32.begin() + i, s32.begin() + std::min(s32.size(), i + 2)));
+    for (size_t i = 0; i < s16.size(); i += 4)
+        add_group(16, std::vector<int32_t>(s16.begin() + i, s16.begin() + std::min(s16.size(), i + 4)));
     h.s_meta.upload(meta, s, "upload streamed plan");
+    h.s_groups.upload(groups, s, "upload streamed plan");
+    h.s_n_groups = n_groups;
     h.s_gidx.upload(g32, s, "upload streamed plan");
     h.s_var_off.upload(var_off, s, "upload streamed plan");
     h.s_var_copy.upload(var_copy, s, "upload streamed plan");
@@ -319,7 +378,7 @@ void stream_solve(ldopf_problem& h) {
     hipLaunchKernelGGL(stream_init_kernel, dim3(1), dim3(64), 0, s, a);
     hip_check(hipGetLastError(), "streamed sweep init");
     const unsigned gblocks = unsigned((a.n + 255) / 256);
-    const int rows = int(std::min<int64_t>(kSBlocks, std::max<int64_t>(1, (a.S + kSWaves - 1) / kSWaves)));
+    const int rows = int(std::min<int64_t>(kSBlocks, std::max<int64_t>(1, (a.n_groups + kSWaves - 1) / kSWaves)));
     hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
     for (int i = 0; i < kSGraph; ++i) {
         hipLaunchKernelGGL(stream_global_kernel, dim3(std::max(gblocks, 1u)), dim3(256), 0, s, a);
