@@ -367,6 +367,8 @@ def main():
     ap.add_argument("--no-rho-balance", action="store_true")
     ap.add_argument("--no-many", action="store_true")
     ap.add_argument("--no-streamed", action="store_true")
+    ap.add_argument("--profile-streamed", type=int, default=0, metavar="SWEEPS",
+                    help="only the 8500-bus feeder on the streamed sweep, SWEEPS fixed sweeps, for rocprofv3 runs")
     args = ap.parse_args()
     if args.cpu_baseline_only:
         _cpu_baseline_child(args.cpu_baseline_only, args.cpu_threads)
@@ -400,6 +402,20 @@ def main():
                           "bytes_per_batched_sweep": batched_bytes_per_sweep(bs),
                           "achieved_GBs": batched_bytes_per_sweep(bs) / (us * 1e-6) / 1e9}))
         b.close()
+        return
+
+    if args.profile_streamed:
+        pnet = make_feeder("8500", 8500)
+        ps = P.ldopf_create(pnet, P.ldopf_default_options(sweep_path=L.LDOPF_PATH_STREAMED,
+                                                          max_iter=args.profile_streamed, check_termination=0),
+                            stream=stream)
+        st = ps.solve()
+        sz = ps.sizes()
+        us = 1e3 * st.sweep_ms / max(1, st.sweeps_computed)
+        print(json.dumps({"sweeps": st.sweeps_computed, "us_per_sweep": us,
+                          "bytes_per_sweep": algorithmic_bytes_per_sweep(sz, 8),
+                          "achieved_GBs": algorithmic_bytes_per_sweep(sz, 8) / (us * 1e-6) / 1e9}))
+        ps.close()
         return
 
     if args.serving_only:
