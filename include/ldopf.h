@@ -275,7 +275,8 @@ LDOPF_API int ldopf_get_sizes(const ldopf_problem* h, ldopf_sizes* out);
 
 /* Replace rho, eps_rel, eps_abs, max_iter, check_termination, history for
  * later solves. Abar_s, bbar_s do not depend on rho, so nothing is
- * recomputed. precision and tuning fields must equal the creation values. */
+ * recomputed. precision, sweep_path and tuning fields must equal the
+ * creation values (else LDOPF_INVALID_ARGUMENT). */
 LDOPF_API int ldopf_set_options(ldopf_problem* h, const ldopf_options* opts);
 
 /*
@@ -283,6 +284,9 @@ LDOPF_API int ldopf_set_options(ldopf_problem* h, const ldopf_options* opts);
  * closed_2, dual update ADMM-3, termination test of Section III-C) from the
  * handle's current state until the test holds or max_iter sweeps ran; the
  * state then holds the last sweep's x, x_s, lambda. Blocks until done.
+ * Runs on the path the handle was created for (ldopf_sizes.sweep_path); on
+ * the streamed sweep the options must keep the literal residual form, fixed
+ * rho and no profile (else LDOPF_UNSUPPORTED).
  * Returns LDOPF_OK, LDOPF_NOT_CONVERGED, LDOPF_NUMERICAL or an error.
  */
 LDOPF_API int ldopf_solve(ldopf_problem* h, ldopf_status* status);
@@ -302,7 +306,8 @@ LDOPF_API int ldopf_solve(ldopf_problem* h, ldopf_status* status);
  * nothing run. Every call on one GPU uses that GPU's one array, so calls
  * that overlap on a GPU would race: this library serializes them (a second
  * caller waits for the first to return). Runs on the handle's device and
- * stream; blocks until done. Returns as ldopf_solve.
+ * stream; blocks until done. Returns as ldopf_solve; LDOPF_UNSUPPORTED for a
+ * handle on the streamed sweep (which allocates its own words).
  */
 LDOPF_API int ldopf_solve_noalloc(ldopf_problem* h, ldopf_status* status);
 
@@ -320,7 +325,8 @@ LDOPF_API int ldopf_solve_noalloc(ldopf_problem* h, ldopf_status* status);
  * the shared launch. Runs on the first problem's stream after every
  * problem's earlier work; blocks until done. Returns LDOPF_OK when every
  * problem did, else the most severe code among them (an error before
- * LDOPF_NOT_CONVERGED).
+ * LDOPF_NOT_CONVERGED). A problem on the streamed sweep cannot share the
+ * launch (LDOPF_UNSUPPORTED).
  */
 LDOPF_API int ldopf_solve_many(ldopf_problem* const* problems, int32_t count, ldopf_status* statuses);
 
@@ -480,7 +486,9 @@ LDOPF_API int ldopf_request_estimate(const ldopf_network* net, const ldopf_optio
  * streams (requests in flight at once). */
 LDOPF_API int ldopf_server_create(int64_t hbm_budget_bytes, int32_t max_slots, ldopf_server** out);
 /* Copy and queue one request; LDOPF_OUT_OF_MEMORY when it alone exceeds the
- * budget. opts: as for ldopf_create (history is not recorded). */
+ * budget. opts: as for ldopf_create (history is not recorded); requests run
+ * on the persistent sweep only (sweep_path LDOPF_PATH_STREAMED is refused
+ * with LDOPF_UNSUPPORTED, and a request too large for it fails at admission). */
 LDOPF_API int ldopf_server_submit(ldopf_server* srv, const ldopf_network* net, const ldopf_options* opts,
                                   int64_t* req_id);
 /* Current state (ldopf_request_state) and, once done, the solve status. */
