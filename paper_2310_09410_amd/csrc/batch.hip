@@ -217,8 +217,10 @@ __global__ __launch_bounds__(256) void batch_pack_kernel(PackArgs a) {
 __global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
     if (a.ctrl[1]) return;
     const int lane = threadIdx.x & 63;
-    const int64_t v0 = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * kVPW;
-    const int sc = blockIdx.y * kTile + lane;
+    const int64_t v0 = int64_t(blockIdx.x) * kVPW;
+    const int tile = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (tile * kTile >= a.Bp) return;
+    const int sc = tile * kTile + lane;
     if (v0 >= a.n || !a.active[sc]) return;
     const float irho = float(1.0 / a.rho);
     const int64_t Bp = a.Bp;
@@ -284,7 +286,11 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
     const int tid = threadIdx.x, lane_id = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int Bp = a.Bp;
-    const int sc_id = blockIdx.y * kTile + lane_id;
+    // the scenario tiles of one chunk-block are adjacent block ids, so the
+    // quarters of each row are read at about the same time
+    const int tiles = a.Bp / kTile;
+    const int tile = int(blockIdx.x) % tiles, bx = int(blockIdx.x) / tiles, nbx = int(gridDim.x) / tiles;
+    const int sc_id = tile * kTile + lane_id;
     const bool on = a.active[sc_id] != 0;
     // a tile whose scenarios have all stopped is skipped (its partial rows
     // are not read: the test runs only for active scenarios)
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
     const CPtr<int32_t> meta = as_const(reinterpret_cast<const int32_t*>(a.meta));
     const CPtr<int32_t> gidx = as_const(a.gidx);
     bool prev_shared = false;  // the last subsystem was of the shared-operator class
-    for (int c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+    for (int c = bx; c < a.n_chunks; c += nbx) {
         const int q1 = chunk_off[c + 1];
         int q = chunk_off[c];
         LocalMeta m = load_meta(meta, q);
@@ -521,10 +527,10 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
     red[(wv * 5 + 3) * 64 + lane_id] = p3;
     red[(wv * 5 + 4) * 64 + lane_id] = p4;
     __syncthreads();
-    double* out = a.part + int64_t(blockIdx.x) * 5 * Bp;
+    double* out = a.part + int64_t(bx) * 5 * Bp;
     for (int e = tid; e < 5 * 64; e += 256) {
         const int qq = e >> 6, l = e & 63;
-        out[qq * Bp + blockIdx.y * kTile + l] = ((red[(0 * 5 + qq) * 64 + l] + red[(1 * 5 + qq) * 64 + l]) +
+        out[qq * Bp + tile * kTile + l] = ((red[(0 * 5 + qq) * 64 + l] + red[(1 * 5 + qq) * 64 + l]) +
                                                  red[(2 * 5 + qq) * 64 + l]) +
                                                 red[(3 * 5 + qq) * 64 + l];
     }
@@ -767,12 +773,13 @@ const void* local_kernel(int rpw) {
 
 void enqueue_sweep(ldopf_batch& h, const BatchArgs& a) {
     const int tiles = h.Bp / kTile;
-    const int64_t per_block = 4 * kVPW;
-    hipLaunchKernelGGL(batch_global_kernel, dim3(unsigned((a.n + per_block - 1) / per_block), tiles), dim3(256), 0,
-                       h.stream, a);
+    // a block's four waves take the same variables for four scenario tiles,
+    // so that the four quarters of each copy row are read together
+    hipLaunchKernelGGL(batch_global_kernel, dim3(unsigned((a.n + kVPW - 1) / kVPW), unsigned((tiles + 3) / 4)), dim3(256),
+                       0, h.stream, a);
     BatchArgs copy = a;
     void* args[] = {&copy};
-    (void)hipLaunchKernel(local_kernel(h.rpw), dim3(h.grid, tiles), dim3(256), args, local_lds(h), h.stream);
+    (void)hipLaunchKernel(local_kernel(h.rpw), dim3(h.grid * tiles), dim3(256), args, local_lds(h), h.stream);
     hipLaunchKernelGGL(batch_reduce_kernel, dim3(tiles * kRedBlocks), dim3(1024), 0, h.stream, a);
 }
 
