@@ -8,8 +8,9 @@ stop the dual test compares per-copy changes of about 1e-7 on values near 1,
 which is FP32's resolution, so the sweep at which an FP32 run first passes
 the test depends on rounding order (a float32 emulation of the same scenario
 stops 12% later with one valid operator factorization and at the FP64 sweep
-with another). It is held within 25%, and the returned state must pass the
-test.
+with another). It is held within 2% of the oracle's for all but at most one
+scenario per feeder and within 25% for that one, and the returned state must
+pass the test.
 """
 import numpy as np
 import pytest
@@ -49,6 +50,7 @@ def test_batch_converged_matches_oracle(gpu, name):
     b = P.ldopf_batch_create(net, f, P.ldopf_default_options(precision=1, max_iter=40000))
     st = b.solve()
     assert st.n_converged == 6 and st.code == 0
+    gaps = []
     for k in range(6):
         ref = _oracle(net, f[k])
         sk = b.scenario(k)
@@ -57,13 +59,19 @@ def test_batch_converged_matches_oracle(gpu, name):
         print(f"{name} scenario {k}: batched FP32 T_stop {sk.iterations}, FP64 oracle {ref.iters} "
               f"({(sk.iterations - ref.iters) / ref.iters:+.2%}); x vs converged oracle "
               f"{rel_err(b.get_global(k), ref.x):.2e}")
-        assert abs(sk.iterations - ref.iters) <= 0.25 * ref.iters, (k, sk.iterations, ref.iters)
+        gap = abs(sk.iterations - ref.iters) / ref.iters
+        gaps.append(gap)
+        assert gap <= 0.25, (k, sk.iterations, ref.iters)
         # the returned state against the oracle after the same number of sweeps
         same = _oracle(net, f[k], max_iter=sk.iterations, check=False)
         x = b.get_global(k)
         obj = float(ref.prep.lp.c @ x)
         assert abs(obj - same.objective) / max(1.0, abs(same.objective)) <= 1e-4
         assert rel_err(x, same.x) <= 1e-4
+    # the FP64 stopping sweep within 2% (Section V-B, Table 5) for all but at
+    # most one scenario per feeder (measured: 11 of these 12 at <= 0.01%,
+    # 13-bus scenario 5 at +15%, the FP32-resolution case above)
+    assert sum(g > 0.02 for g in gaps) <= 1, gaps
 
 
 def test_batch_fixed_sweeps_match_oracle(gpu):
@@ -97,6 +105,31 @@ def test_batch_alone_equals_in_the_mix(gpu):
     xm, lm = mix.get_local(4)
     np.testing.assert_array_equal(xa, xm)
     np.testing.assert_array_equal(la, lm)
+
+
+def test_batch_ragged_tile_count(gpu):
+    """130 scenarios: three 64-scenario tiles (a count that is not a
+    multiple of the four tiles a global-update block takes) and a padded last
+    tile; scenarios from every tile against the oracle after the same sweeps,
+    and the last scenario equal bit for bit to a batch of its own."""
+    P = gpu
+    net = feeder("123")
+    f = _factors(net, 130, 77)
+    T = 60
+    opts = P.ldopf_default_options(precision=1, max_iter=T, check_termination=0)
+    b = P.ldopf_batch_create(net, f, opts)
+    s = b.sizes()
+    assert s.n_scen == 130 and s.n_scen_padded == 192
+    assert b.solve().sweeps == T
+    for k in (0, 63, 64, 127, 128, 129):
+        ref = _oracle(net, f[k], max_iter=T, check=False)
+        xs, lam = b.get_local(k)
+        assert b.scenario(k).iterations == T
+        assert rel_err(b.get_global(k), ref.x) <= 1e-4
+        assert rel_err(xs, ref.xs) <= 1e-4
+    alone = P.ldopf_batch_create(net, f[129:130], opts)
+    alone.solve()
+    np.testing.assert_array_equal(alone.get_global(0), b.get_global(129))
 
 
 def test_batch_tuner_keeps_results(gpu, tmp_path):
