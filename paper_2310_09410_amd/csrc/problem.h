@@ -63,7 +63,7 @@ struct ldopf_problem {
     int64_t s_n_groups = 0;
     DevBuf<int64_t> s_meta, s_ctrl;
     DevBuf<int32_t> s_gidx, s_var_off, s_var_copy, s_groups;
-    DevBuf<double> s_part;
+    DevBuf<double> s_part, s_x2;
     hipGraph_t s_graph = nullptr;
     hipGraphExec_t s_exec = nullptr;
 
@@ -71,7 +71,7 @@ struct ldopf_problem {
     // serving runtime's slot streams, which outlive their problems)
     void use_stream_ordered_memory(hipStream_t s) {
         for (DevBuf<double>* q : {&A, &b, &basis, &abar, &bbar, &c, &lo, &hi, &cnt, &xs, &lam, &x, &hist, &rpart, &gpart,
-                                  &prof, &rholog, &bagg, &s_part})
+                                  &prof, &rholog, &bagg, &s_part, &s_x2})
             q->ordered = s;
         for (DevBuf<int32_t>* q : {&ns, &ms, &rank_d, &flags, &row_canon, &var_gid, &var_slot, &var_slot_lo, &var_slot_hi,
                                    &s_gidx, &s_var_off, &s_var_copy, &s_groups})

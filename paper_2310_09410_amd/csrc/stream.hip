@@ -9,12 +9,14 @@
 // per subsystem, a lane per row: t_k = sum_j W_kj v_j by a butterfly sum over
 // the wave, then y_j = bbar_j + v_j - sum_k W_kj t_k in mode 1 or bbar_j +
 // sum_k W_kj t_k in mode 0, with W the K_s rows of the precomputed basis that
-// span the smaller of the row space and its complement), and the residual
-// sums over the blocks' partial rows with the test, in a fixed order. A
-// launch after the sweep that passed the test returns at once, so C sweeps
-// are captured in one HIP graph and the host replays it until the test
-// holds. FP64 throughout; the returned state is that of the sweep that
-// passed the test.
+// span the smaller of the row space and its complement), and the test of
+// Section III-C, which block 0 of the next global update runs on the local
+// update's per-block residual sums, in a fixed order. The global update of
+// sweep k writes x into the half k % 2 of a two-part buffer, so the x of
+// the sweep that passed the test survives the next sweep's global update.
+// A launch after the stop returns at once, so C sweeps are captured in one
+// HIP graph and the host replays it until the test holds. FP64 throughout;
+// the returned state is that of the sweep that passed the test.
 
 #include <hip/hip_runtime.h>
 
@@ -48,11 +50,11 @@ struct StreamArgs {
     const double* lo;
     const double* hi;
     const double* cnt;
-    double* x;
+    double* x;  // the half of the two-part x buffer this sweep writes (global) or reads (local)
     double* xs;
     double* lam;
     double* part;  // [kSBlocks][5]
-    int64_t* ctrl; // [0] sweeps done, [1] stopped
+    int64_t* ctrl; // [0] the sweep being computed (tested at the next global update), [1] stopped
     double* hist;
     int64_t hist_cap;
     SweepStatus* st;
@@ -81,10 +83,68 @@ __global__ void stream_init_kernel(StreamArgs a) {
     st->rho_changes = 0;
 }
 
+// Block 0 of a global update: the test of the sweep whose local update ran
+// last (its blocks' residual rows in a fixed order: thread r takes rows r,
+// r + 256, ..., then butterfly sums over each wave and the waves in order),
+// its history row and status; then either the stop or the next sweep's
+// number. Every thread of the block calls it.
+__device__ void stream_test(const StreamArgs& a, int rows) {
+    __shared__ double red[4][5];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = a.ctrl[0];
+    if (t >= 1) {
+        double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int r = threadIdx.x; r < rows; r += 256)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) p[q] += a.part[int64_t(r) * 5 + q];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) p[q] = wave_sum(p[q]);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) red[wv][q] = p[q];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (t < 1) {
+        a.ctrl[0] = 1;
+        return;
+    }
+    double d[5];
+    for (int q = 0; q < 5; ++q) d[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    const double sq = sqrt(double(a.nloc));
+    const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
+    const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
+    const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
+    if (t <= a.hist_cap) {
+        double* h = a.hist + (t - 1) * 4;
+        h[0] = pres;
+        h[1] = dres;
+        h[2] = eps_p;
+        h[3] = eps_d;
+    }
+    const bool conv = pres <= eps_p && dres <= eps_d;
+    const bool bad = !isfinite(d[0] + d[1] + d[2] + d[3] + d[4]);
+    SweepStatus* st = a.st;
+    st->iters = t;
+    st->computed = t;
+    st->converged = conv ? 1 : 0;
+    st->pres = pres;
+    st->dres = dres;
+    st->eps_p = eps_p;
+    st->eps_d = eps_d;
+    if (bad) st->flags |= 2;
+    if (bad || (a.check && conv) || t >= a.max_iter)
+        a.ctrl[1] = 1;
+    else
+        a.ctrl[0] = t + 1;
+}
+
 // closed_1: x_i = clip((sum_c x_s,c - (c_i + sum_c lambda_c) / rho) / N_i) over
-// the copies c of variable i, in copy order (a NaN passes the clip).
-__global__ __launch_bounds__(256) void stream_global_kernel(StreamArgs a) {
+// the copies c of variable i, in copy order (a NaN passes the clip); block 0
+// first runs the test of the previous sweep.
+__global__ __launch_bounds__(256) void stream_global_kernel(StreamArgs a, int rows) {
     if (a.ctrl[1]) return;
+    if (blockIdx.x == 0) stream_test(a, rows);
     const int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (v >= a.n) return;
     double sx = 0.0, sl = 0.0;
@@ -198,56 +258,6 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
     }
 }
 
-// The partial rows in a fixed order (thread r takes row r, butterfly over
-// each wave, then the waves in order), the test, history and status.
-__global__ __launch_bounds__(1024) void stream_test_kernel(StreamArgs a, int rows) {
-    if (a.ctrl[1]) return;
-    __shared__ double red[16][5];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int r = threadIdx.x; r < rows; r += 1024)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) p[q] += a.part[int64_t(r) * 5 + q];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) p[q] = wave_sum(p[q]);
-    if (lane == 0)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) red[wv][q] = p[q];
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double d[5];
-    for (int q = 0; q < 5; ++q) {
-        double t = 0.0;
-        for (int w = 0; w < 16; ++w) t += red[w][q];
-        d[q] = t;
-    }
-    const int64_t k = a.ctrl[0] + 1;
-    const double sq = sqrt(double(a.nloc));
-    const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
-    const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
-    const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
-    if (k <= a.hist_cap) {
-        double* h = a.hist + (k - 1) * 4;
-        h[0] = pres;
-        h[1] = dres;
-        h[2] = eps_p;
-        h[3] = eps_d;
-    }
-    const bool conv = pres <= eps_p && dres <= eps_d;
-    const bool bad = !isfinite(d[0] + d[1] + d[2] + d[3] + d[4]);
-    SweepStatus* st = a.st;
-    st->iters = k;
-    st->computed = k;
-    st->converged = conv ? 1 : 0;
-    st->pres = pres;
-    st->dres = dres;
-    st->eps_p = eps_p;
-    st->eps_d = eps_d;
-    if (bad) st->flags |= 2;
-    a.ctrl[0] = k;
-    a.ctrl[1] = (bad || (a.check && conv) || k >= a.max_iter) ? 1 : 0;
-}
-
 StreamArgs stream_args(ldopf_problem& h) {
     StreamArgs a{};
     a.S = h.lp.S;
@@ -265,7 +275,7 @@ StreamArgs stream_args(ldopf_problem& h) {
     a.lo = h.lo.p;
     a.hi = h.hi.p;
     a.cnt = h.cnt.p;
-    a.x = h.x.p;
+    a.x = h.s_x2.p;
     a.xs = h.xs.p;
     a.lam = h.lam.p;
     a.part = h.s_part.p;
@@ -360,6 +370,7 @@ void stream_prepare(ldopf_problem& h) {
     h.s_var_off.upload(var_off, s, "upload streamed plan");
     h.s_var_copy.upload(var_copy, s, "upload streamed plan");
     h.s_part.alloc(size_t(kSBlocks) * 5, "streamed residual rows");
+    h.s_x2.alloc(size_t(2) * lp.n, "streamed x halves");
     h.s_ctrl.alloc(2, "streamed control");
     h.s_nq = max_n <= 64 ? 1 : (max_n <= 256 ? 4 : 16);
     h.streamed = true;
@@ -380,12 +391,14 @@ void stream_solve(ldopf_problem& h) {
     const unsigned gblocks = unsigned((a.n + 255) / 256);
     const int rows = int(std::min<int64_t>(kSBlocks, std::max<int64_t>(1, (a.n_groups + kSWaves - 1) / kSWaves)));
     hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
+    // node i of a graph computes sweep 32 g + i + 1 (every graph starts after
+    // a multiple of kSGraph sweeps, an even number): its x half is (i + 1) % 2
     for (int i = 0; i < kSGraph; ++i) {
-        hipLaunchKernelGGL(stream_global_kernel, dim3(std::max(gblocks, 1u)), dim3(256), 0, s, a);
-        StreamArgs copy = a;
-        void* args[] = {&copy};
+        StreamArgs ai = a;
+        ai.x = a.x + int64_t((i + 1) % 2) * a.n;
+        hipLaunchKernelGGL(stream_global_kernel, dim3(std::max(gblocks, 1u)), dim3(256), 0, s, ai, rows);
+        void* args[] = {&ai};
         (void)hipLaunchKernel(local_kernel(h.s_nq), dim3(rows), dim3(64 * kSWaves), args, 0, s);
-        hipLaunchKernelGGL(stream_test_kernel, dim3(1), dim3(1024), 0, s, a, rows);
     }
     hip_check(hipStreamEndCapture(s, &h.s_graph), "graph capture");
     hip_check(hipGraphInstantiate(&h.s_exec, h.s_graph, nullptr, nullptr, 0), "graph instantiate");
@@ -399,6 +412,10 @@ void stream_solve(ldopf_problem& h) {
         // every sweep of a graph that did not stop advances the count
         if (ctrl[0] != before + kSGraph) fail(LDOPF_DEVICE_ERROR, "the streamed sweep count did not advance");
     }
+    // the x of the returned sweep (ctrl[0] when stopped) into the handle's x
+    if (ctrl[0] >= 1)
+        hip_check(hipMemcpyAsync(h.x.p, h.s_x2.p + (ctrl[0] % 2) * a.n, size_t(a.n) * 8, hipMemcpyDeviceToDevice, s),
+                  "copy x");
 }
 
 }  // namespace ldopf
