@@ -46,6 +46,12 @@ def algorithmic_bytes_per_sweep(sizes, w: int) -> float:
     return (w * (sizes.rank_words + sizes.n_local) + sizes.n_local * (4 * w + 4) + sizes.n * 5 * w)
 
 
+def dense_equivalent_bytes_per_sweep(sizes, w: int) -> float:
+    """The same compulsory traffic with the dense n_s x n_s operator Abar_s in
+    place of its rank form (the accounting of a dense matvec per subsystem)."""
+    return (w * (sizes.op_words + sizes.n_local) + sizes.n_local * (4 * w + 4) + sizes.n * 5 * w)
+
+
 def kernel_sha() -> str:
     """Hash of the sweep kernel's source with comments and whitespace removed,
     so that the stored counters stay valid across comment-only edits and
@@ -490,7 +496,10 @@ def main():
                      "launch_ms": launch_ms,
                      "achieved_is": "algorithmic bytes per sweep / time per sweep (operators and state stay in LDS)",
                      "measured_hbm_GBs": None, "limiter": "exchange latency between workgroups, block barriers "
-                                                          "and dependent LDS reads, not HBM bandwidth"},
+                                                          "and dependent LDS reads, not HBM bandwidth",
+                     "dense_equivalent_bytes_per_sweep": dense_equivalent_bytes_per_sweep(sizes, 8),
+                     "dense_equivalent_GBs": dense_equivalent_bytes_per_sweep(sizes, 8) * sweeps_per_launch
+                                             / (launch_ms * 1e-3) / 1e9},
     }
     if rec["roofline"]["traffic"] is not None:
         rec["roofline"]["measured_hbm_GBs"] = rec["roofline"]["traffic"] / (launch_ms * 1e-3) / 1e9
