@@ -73,7 +73,7 @@ typedef enum ldopf_code {
     LDOPF_DEVICE_ERROR = -6,           /* a HIP call or kernel failed */
     LDOPF_NUMERICAL = -7,              /* NaN or Inf in the iterate or residuals */
     LDOPF_BUFFER_TOO_SMALL = -8,       /* output capacity below the needed size */
-    LDOPF_UNSUPPORTED = -9             /* valid request this build does not run */
+    LDOPF_UNSUPPORTED = -9             /* valid request this library does not run */
 } ldopf_code;
 
 typedef enum ldopf_precision {
