@@ -139,6 +139,15 @@ def test_too_large_for_the_persistent_sweep(gpu):
     assert rel_err(prob.get_global(), ref.x) <= 1e-6
     assert rel_err(xs, ref.xs) <= 1e-6
     assert rel_err(lam, ref.lam) <= 1e-6
+    # in the FP32-mixed form the same feeder takes half the LDS and stays on
+    # the persistent sweep
+    p32 = P.ldopf_create(net, P.ldopf_default_options(max_iter=T, check_termination=0,
+                                                      precision=P.ldopf.LDOPF_FP32_MIXED))
+    assert p32.sizes().sweep_path == P.ldopf.LDOPF_PATH_PERSISTENT
+    p32.solve()
+    xs32, _ = p32.get_local()
+    assert rel_err(p32.get_global(), ref.x) <= 1e-4
+    assert rel_err(xs32, ref.xs) <= 1e-4
 
 
 def test_streamed_refusals(gpu):
