@@ -132,6 +132,25 @@ def test_batch_ragged_tile_count(gpu):
     np.testing.assert_array_equal(alone.get_global(0), b.get_global(129))
 
 
+def test_batch_8500bus_feeder(gpu):
+    """The largest feeder as a batch: 8500 buses x 128 scenarios (per-bus
+    factors as in the benchmark), 20 fixed sweeps; the lightest and heaviest
+    scenarios and one between against the oracle."""
+    P = gpu
+    net = feeder("8500")
+    from synth import scenario_factors
+    f = scenario_factors(net, 128, base_seed=8500 * 1000)
+    T = 20
+    b = P.ldopf_batch_create(net, f, P.ldopf_default_options(precision=1, max_iter=T, check_termination=0))
+    assert b.solve().sweeps == T
+    mean = f.mean(axis=1)
+    for k in sorted({int(np.argmin(mean)), int(np.argmax(mean)), 77}):
+        ref = _oracle(net, f[k], max_iter=T, check=False)
+        xs, lam = b.get_local(k)
+        assert rel_err(b.get_global(k), ref.x) <= 1e-4, k
+        assert rel_err(xs, ref.xs) <= 1e-4, k
+
+
 def test_batch_tuner_keeps_results(gpu, tmp_path):
     P = gpu
     net = feeder("123")
