@@ -103,6 +103,26 @@ def test_streamed_large_subsystem(gpu):
     assert rel_err(lam, ref.lam) <= 1e-6
 
 
+def test_streamed_mid_size_subsystems(gpu):
+    """The 123-bus feeder merged into 79 subtrees of up to 111 variables
+    (the kernel variant with up to four rows per lane), against the oracle on
+    the same consensus LP."""
+    from oracle import admm
+    from test_gpu_large_subsystems import _create, subtree_lp
+    P = gpu
+    lp = subtree_lp(feeder("123"), 6)
+    assert 64 < max(len(s.gidx) for s in lp.subs) <= 256
+    T = 100
+    prob = _create(P, lp, _streamed(P, max_iter=T, check_termination=0))
+    assert prob.solve().iterations == T
+    ref = admm.solve(lp, max_iter=T, check=False)
+    xs, lam = prob.get_local()
+    assert rel_err(prob.get_global(), ref.x) <= 1e-6
+    assert rel_err(xs, ref.xs) <= 1e-6
+    assert rel_err(lam, ref.lam) <= 1e-6
+    np.testing.assert_allclose(prob.get_history(), ref.history, rtol=1e-6, atol=1e-12)
+
+
 def test_warm_start_streamed(gpu):
     """150 sweeps == 60 sweeps, fetch, warm start, 90 sweeps (bit for bit)."""
     P = gpu
