@@ -196,6 +196,27 @@ def test_batch_refuses_what_it_does_not_run(field):
     assert e.value.code == -9
 
 
+def test_batch_argument_checks_before_any_device_work():
+    """ldopf_batch_create checks the scenario count, the form and the load
+    factors on the host before touching the device."""
+    import paper_2310_09410_amd as P
+    net = feeder("13")
+    nl = int(net["n_load"])
+    o32 = P.ldopf_default_options(precision=1)
+    for n_scen in (0, 1025):
+        with pytest.raises(P.LdopfError) as e:
+            P.ldopf_batch_create(net, np.ones((n_scen, nl)), o32)
+        assert e.value.code == -1
+    with pytest.raises(P.LdopfError) as e:
+        P.ldopf_batch_create(net, np.ones((2, nl)), P.ldopf_default_options(precision=0))
+    assert e.value.code == -9
+    bad = np.ones((2, nl))
+    bad[1, 0] = np.nan
+    with pytest.raises(P.LdopfError) as e:
+        P.ldopf_batch_create(net, bad, o32)
+    assert e.value.code == -1
+
+
 @pytest.mark.parametrize("name", ["13", "123", "2500", "8500"])
 def test_request_estimate_plans_on_the_host(name):
     """The serving admission's estimate assembles, decomposes and plans the
