@@ -18,8 +18,14 @@
 // sweep (global update, local update, dual update) runs in FP32; residual
 // sums, the termination test and the per-scenario masks in FP64. Each
 // scenario stops at its own first sweep that passes the test (Section III-C)
-// and keeps that state while the others continue. C sweeps are captured in
-// one HIP graph; the host replays it until every scenario has stopped.
+// and keeps that state while the others continue. Two launches per sweep:
+// the global update, whose first blocks also reduce the residual sums of the
+// previous sweep and run its test, and the local update; the global update
+// of sweep k writes x into the half k % 2 of a two-part buffer, so the x of
+// a scenario's stopping sweep survives the next sweep's global update (the
+// local update of that sweep skips the scenario, so its x_s and lambda stay
+// too). C sweeps are captured in one HIP graph (C even, the half fixed per
+// node); the host replays it until every scenario has stopped.
 //
 // State layout in HBM: row-major [copy or variable][scenario], scenarios
 // padded to Bp (a multiple of 64), so a wave reads 64 consecutive scenarios.
@@ -50,7 +56,7 @@ namespace {
 constexpr int kTile = 64;  // scenarios per wave
 constexpr int kZS = 80;    // LDS row stride (floats) of the local update
 constexpr int kVPW = 4;    // variables per wave in the global update
-constexpr int kRedBlocks = 8;  // reduction blocks per scenario tile
+constexpr int kRedBlocks = 16;  // reduction blocks (four waves each) per scenario tile
 constexpr int kKB = 1;         // operator rows per load batch of the per-scenario class
 
 struct PrecomputeBatchArgs {
@@ -137,7 +143,7 @@ struct BatchArgs {
     const float* lo;
     const float* hi;
     const float* invN;
-    float* X;
+    float* X;  // the half of the two-part x buffer this sweep writes (global) and reads (local)
     float* XS;
     float* LAM;
     const float* BB;
@@ -159,7 +165,8 @@ struct BatchArgs {
     int64_t* iters;    // [Bp]
     double* res;       // [Bp][4]
     int32_t* sflags;   // [Bp]
-    int64_t* ctrl;     // [0] sweeps done, [1] all done, [2] active count, [3] arrivals
+    int64_t* ctrl;     // [0] the sweep being computed (tested by the next global update), [1] all done,
+                       // [2] active count, [3] arrivals
     int64_t max_iter;
     int32_t check;
     double rho, eps_rel, eps_abs;
@@ -209,16 +216,143 @@ __global__ __launch_bounds__(256) void batch_pack_kernel(PackArgs a) {
     }
 }
 
+// Residual sums per scenario over the local blocks' partial rows of the
+// previous sweep, and its termination test, in the first blocks of the next
+// global update (beside the blocks of the update itself). Two levels:
+// kRedBlocks blocks per scenario tile each add a contiguous slice of the rows
+// (wave w adds rows w, w + 4, ...; then the four waves in order) and store
+// the slice sums; the last block of the tile to finish (a ticket per tile)
+// adds the slices in order and runs the test and the masks; the last tile to
+// finish either stops the batch or numbers the sweep the update computes.
+// The order of every sum is fixed. The update blocks of the same launch may
+// or may not see a scenario stop: either way they write the other half of x,
+// and the local update after them sees the masks.
+// Words read by other blocks of the same launch (the slice sums) go through
+// the device's coherence point (agent-scope relaxed atomics); a block makes
+// them visible before it takes its ticket by waiting for its own stores to
+// complete (s_waitcnt 0) instead of a device-scope release fence, which would
+// write back the whole L2 of its XCD.
+__device__ inline void st_dev(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_dev(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ inline void batch_test(const BatchArgs& a, int rblock) {
+    __shared__ double red[4][5][kTile];
+    __shared__ int last;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tiles = a.Bp / kTile;
+    const int tile = rblock / kRedBlocks, rb = rblock % kRedBlocks;
+    const int sc = tile * kTile + lane;
+    // the sweep the previous local update computed (0 before the first one);
+    // used before this block's ticket, so read before the last block of the
+    // launch changes it
+    const int64_t t = a.ctrl[0];
+    // a tile whose scenarios have all stopped reads nothing, but still
+    // arrives at the counts below
+    const bool any = __syncthreads_or(t >= 1 && a.active[sc] != 0);
+    const int per = (a.part_rows + kRedBlocks - 1) / kRedBlocks;
+    const int r0 = min(a.part_rows, rb * per), r1 = any ? min(a.part_rows, r0 + per) : r0;
+    double acc[5] = {0, 0, 0, 0, 0};
+    int r = r0 + wv;
+    for (; r + 4 < r1; r += 8) {
+        double u[5], w[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            u[q] = a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
+            w[q] = a.part[(int64_t(r + 4) * 5 + q) * a.Bp + sc];
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] += u[q] + w[q];
+    }
+    if (r < r1)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[q] += a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) red[wv][q][lane] = acc[q];
+    __syncthreads();
+    double* slice = a.part2 + int64_t(tile) * kRedBlocks * 5 * kTile;
+    if (wv == 0) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+            st_dev(slice + (rb * 5 + q) * kTile + lane,
+                   ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane]);
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&a.tick[tile], 1) == kRedBlocks - 1;
+    __syncthreads();
+    if (!last) return;
+    if (wv == 0) {
+        int still = sc < a.B && a.active[sc] != 0;
+        if (t >= 1 && still) {
+            double d[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                double u = 0.0;
+                for (int b2 = 0; b2 < kRedBlocks; ++b2) u += ld_dev(slice + (b2 * 5 + q) * kTile + lane);
+                d[q] = u;
+            }
+            const double sq = sqrt(double(a.nloc));
+            const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
+            const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
+            const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
+            a.iters[sc] = t;
+            a.res[sc * 4 + 0] = pres;
+            a.res[sc * 4 + 1] = dres;
+            a.res[sc * 4 + 2] = eps_p;
+            a.res[sc * 4 + 3] = eps_d;
+            const bool conv = pres <= eps_p && dres <= eps_d;
+            a.conv[sc] = conv;
+            const bool bad = !isfinite(d[0] + d[1] + d[2] + d[3] + d[4]);
+            if (bad) a.sflags[sc] |= 2;
+            still = !(bad || (a.check && conv));
+            if (!still) a.active[sc] = 0;
+        }
+        const unsigned long long ball = __ballot(still);
+        if (lane == 0) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), (unsigned long long)__popcll(ball));
+            a.tick[tile] = 0;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        const unsigned long long prev = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[3]), 1ull);
+        if (prev == unsigned(tiles) - 1) {
+            const long long left = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), 0ull);
+            a.ctrl[2] = 0;
+            a.ctrl[3] = 0;
+            if (t >= 1 && (left == 0 || t >= a.max_iter))
+                a.ctrl[1] = 1;
+            else
+                a.ctrl[0] = t + 1;
+        }
+    }
+}
+
 // Global update (closed_1): a wave takes kVPW consecutive variables for one
-// 64-scenario tile. The first four copies of each variable come from a
-// padded table (one 16-byte read per variable) so that all their loads are
-// in flight together; further copies, if any, from the CSR lists. Copies are
-// added in CSR order.
+// 64-scenario tile; the four waves of a block take the same variables for
+// four tiles. The first four copies of each variable come from a padded
+// table (one 16-byte read per variable) so that all their loads are in flight
+// together; further copies, if any, from the CSR lists. Copies are added in
+// CSR order. The first kRedBlocks blocks per tile run the test of the
+// previous sweep instead.
 __global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
     if (a.ctrl[1]) return;
+    const int n_red = (a.Bp / kTile) * kRedBlocks;
+    if (int(blockIdx.x) < n_red) {
+        batch_test(a, int(blockIdx.x));
+        return;
+    }
     const int lane = threadIdx.x & 63;
-    const int64_t v0 = int64_t(blockIdx.x) * kVPW;
-    const int tile = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int64_t nvb = (a.n + kVPW - 1) / kVPW, b = int64_t(blockIdx.x) - n_red;
+    const int64_t v0 = (b % nvb) * kVPW;
+    const int tile = int(b / nvb) * 4 + (threadIdx.x >> 6);
     if (tile * kTile >= a.Bp) return;
     const int sc = tile * kTile + lane;
     if (v0 >= a.n || !a.active[sc]) return;
@@ -536,118 +670,6 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
     }
 }
 
-// Residual sums per scenario over the local blocks' partial rows, in two
-// levels: kRedBlocks blocks per scenario tile each add a contiguous slice of
-// the rows (16 waves, wave w adds rows w, w + 16, ...; then the waves in
-// order) and store the slice sums; the last block of the tile to finish (a
-// ticket per tile) adds the slices in order and runs the termination test,
-// the masks; the last tile to finish advances the sweep counter and decides
-// whether the batch is done. The order of every sum is fixed.
-// Words read by other blocks of the same launch (the slice sums) go through
-// the device's coherence point (agent-scope relaxed atomics); a block makes
-// them visible before it takes its ticket by waiting for its own stores to
-// complete (s_waitcnt 0) instead of a device-scope release fence, which would
-// write back the whole L2 of its XCD.
-__device__ inline void st_dev(double* p, double v) {
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double ld_dev(const double* p) {
-    return __longlong_as_double((long long)__hip_atomic_load(
-        reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-
-__global__ __launch_bounds__(1024) void batch_reduce_kernel(BatchArgs a) {
-    if (a.ctrl[1]) return;
-    __shared__ double red[16][5][64];
-    __shared__ int last;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int tile = blockIdx.x / kRedBlocks, rb = blockIdx.x % kRedBlocks;
-    const int sc = tile * kTile + lane;
-    // a tile whose scenarios have all stopped reads nothing, but still
-    // arrives at the counts below
-    const bool any = __syncthreads_or(a.active[sc] != 0);
-    const int per = (a.part_rows + kRedBlocks - 1) / kRedBlocks;
-    const int r0 = min(a.part_rows, rb * per), r1 = any ? min(a.part_rows, r0 + per) : r0;
-    double acc[5] = {0, 0, 0, 0, 0};
-    int r = r0 + wv;
-    for (; r + 16 < r1; r += 32) {
-        double u[5], w[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            u[q] = a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
-            w[q] = a.part[(int64_t(r + 16) * 5 + q) * a.Bp + sc];
-        }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) acc[q] += u[q] + w[q];
-    }
-    if (r < r1)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) acc[q] += a.part[(int64_t(r) * 5 + q) * a.Bp + sc];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) red[wv][q][lane] = acc[q];
-    __syncthreads();
-    double* slice = a.part2 + int64_t(tile) * kRedBlocks * 5 * kTile;
-    if (wv == 0)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            double t = 0.0;
-            for (int w = 0; w < 16; ++w) t += red[w][q][lane];
-            st_dev(slice + (rb * 5 + q) * kTile + lane, t);
-        }
-    __syncthreads();
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&a.tick[tile], 1) == kRedBlocks - 1;
-    __syncthreads();
-    if (!last) return;
-    const int64_t t_now = a.ctrl[0] + 1;
-    if (wv == 0) {
-        double d[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            double t = 0.0;
-            for (int b2 = 0; b2 < kRedBlocks; ++b2) t += ld_dev(slice + (b2 * 5 + q) * kTile + lane);
-            d[q] = t;
-        }
-        int still = 0;
-        if (sc < a.B && a.active[sc]) {
-            const double sq = sqrt(double(a.nloc));
-            const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
-            const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
-            const double eps_d = sq * a.eps_abs + a.eps_rel * sqrt(d[4]);
-            a.iters[sc] = t_now;
-            a.res[sc * 4 + 0] = pres;
-            a.res[sc * 4 + 1] = dres;
-            a.res[sc * 4 + 2] = eps_p;
-            a.res[sc * 4 + 3] = eps_d;
-            const bool conv = pres <= eps_p && dres <= eps_d;
-            a.conv[sc] = conv;
-            const bool bad = !isfinite(d[0] + d[1] + d[2] + d[3] + d[4]);
-            if (bad) a.sflags[sc] |= 2;
-            still = !(bad || (a.check && conv));
-            if (!still) a.active[sc] = 0;
-        }
-        const unsigned long long ball = __ballot(still);
-        if (lane == 0) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), (unsigned long long)__popcll(ball));
-            a.tick[tile] = 0;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_s_waitcnt(0);
-        const unsigned long long prev = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[3]), 1ull);
-        if (prev == unsigned(a.Bp / kTile) - 1) {
-            const long long left = atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl[2]), 0ull);
-            a.ctrl[0] = t_now;
-            a.ctrl[2] = 0;
-            a.ctrl[3] = 0;
-            a.ctrl[1] = (left == 0 || t_now >= a.max_iter) ? 1 : 0;
-        }
-    }
-}
-
 __global__ void batch_init_kernel(BatchArgs a, const double* x_init) {
     // initial point of Section V-A for every scenario; plain stores
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -657,7 +679,7 @@ __global__ void batch_init_kernel(BatchArgs a, const double* x_init) {
         a.XS[i] = float(x_init[a.gidx[c]]);
         a.LAM[i] = 0.f;
     }
-    if (i < a.n * a.Bp) a.X[i] = 0.f;
+    if (i < 2 * a.n * a.Bp) a.X[i] = 0.f;  // both halves
     if (i < a.Bp) {
         const int sc = int(i);
         a.active[sc] = sc < a.B ? 1 : 0;
@@ -773,14 +795,14 @@ const void* local_kernel(int rpw) {
 
 void enqueue_sweep(ldopf_batch& h, const BatchArgs& a) {
     const int tiles = h.Bp / kTile;
-    // a block's four waves take the same variables for four scenario tiles,
-    // so that the four quarters of each copy row are read together
-    hipLaunchKernelGGL(batch_global_kernel, dim3(unsigned((a.n + kVPW - 1) / kVPW), unsigned((tiles + 3) / 4)), dim3(256),
-                       0, h.stream, a);
+    // the test blocks first, then the update blocks: a block's four waves
+    // take the same variables for four scenario tiles, so that the four
+    // quarters of each copy row are read together
+    const int64_t update_blocks = (a.n + kVPW - 1) / kVPW * ((tiles + 3) / 4);
+    hipLaunchKernelGGL(batch_global_kernel, dim3(unsigned(tiles * kRedBlocks + update_blocks)), dim3(256), 0, h.stream, a);
     BatchArgs copy = a;
     void* args[] = {&copy};
     (void)hipLaunchKernel(local_kernel(h.rpw), dim3(h.grid * tiles), dim3(256), args, local_lds(h), h.stream);
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(tiles * kRedBlocks), dim3(1024), 0, h.stream, a);
 }
 
 // Chunks of the subsystem order: consecutive subsystems up to rows_per_chunk copies.
@@ -835,14 +857,19 @@ void build_graph(ldopf_batch& h) {
     if (h.exec) return;
     const BatchArgs a = batch_args(h);
     hip_check(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal), "graph capture");
-    for (int i = 0; i < h.graph_sweeps; ++i) enqueue_sweep(h, a);
+    // node i computes sweep C g + i + 1 of the g-th replay: x half (i + 1) % 2
+    for (int i = 0; i < h.graph_sweeps; ++i) {
+        BatchArgs ai = a;
+        ai.X = a.X + int64_t((i + 1) & 1) * a.n * a.Bp;
+        enqueue_sweep(h, ai);
+    }
     hip_check(hipStreamEndCapture(h.stream, &h.graph), "graph capture");
     hip_check(hipGraphInstantiate(&h.exec, h.graph, nullptr, nullptr, 0), "graph instantiate");
 }
 
 void batch_reset(ldopf_batch& h) {
     const BatchArgs a = batch_args(h);
-    const int64_t total = std::max<int64_t>(int64_t(h.lp.gidx.size()), h.lp.n) * h.Bp;
+    const int64_t total = std::max<int64_t>(int64_t(h.lp.gidx.size()), 2 * h.lp.n) * h.Bp;
     hipLaunchKernelGGL(batch_init_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, h.stream, a, h.x_init.p);
     hip_check(hipGetLastError(), "batch init");
     hip_check(hipStreamSynchronize(h.stream), "batch init");
@@ -1191,7 +1218,7 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             h->hi.upload(hi, s, "upload hi");
             h->invN.upload(invN, s, "upload counts");
             h->x_init.upload(L.x_init, s, "upload start");
-            h->X.alloc(size_t(L.n) * Bp, "x");
+            h->X.alloc(2 * size_t(L.n) * Bp, "x");
             h->XS.alloc(size_t(nloc) * Bp, "x_s");
             h->LAM.alloc(size_t(nloc) * Bp, "lambda");
             h->active.alloc(Bp, "masks");
@@ -1281,8 +1308,12 @@ int ldopf_batch_get_global(const ldopf_batch* h, int32_t scen, double* x, int64_
         need(x, "x");
         if (scen < 0 || scen >= h->B) fail(LDOPF_INVALID_ARGUMENT, "scenario out of range");
         if (cap < h->lp.n) fail(LDOPF_BUFFER_TOO_SMALL, "x needs n entries");
+        // x of the scenario's returned sweep: the half of its parity
+        int64_t it = 0;
+        hip_check(hipMemcpy(&it, h->iters.p + scen, 8, hipMemcpyDeviceToHost), "download");
+        const float* xh = h->X.p + (it & 1) * h->lp.n * h->Bp;
         std::vector<float> col(h->lp.n);
-        hip_check(hipMemcpy2D(col.data(), 4, h->X.p + scen, size_t(h->Bp) * 4, 4, h->lp.n, hipMemcpyDeviceToHost), "download x");
+        hip_check(hipMemcpy2D(col.data(), 4, xh + scen, size_t(h->Bp) * 4, 4, h->lp.n, hipMemcpyDeviceToHost), "download x");
         for (int64_t v = 0; v < h->lp.n; ++v) x[v] = col[v];
     });
 }
