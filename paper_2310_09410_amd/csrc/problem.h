@@ -57,12 +57,14 @@ struct ldopf_problem {
     DevBuf<SweepStatus> st;
     // streamed sweep (a problem too large for the persistent sweep's LDS):
     // per-subsystem words, copies as 32-bit indices, the copies of each
-    // variable (CSR), the blocks' residual rows, control words, the graph
+    // variable (CSR, and the first four padded), the blocks' residual rows,
+    // control words, the graph
     bool streamed = false;
     int32_t s_nq = 1;
     int64_t s_n_groups = 0;
     DevBuf<int64_t> s_meta, s_ctrl;
     DevBuf<int32_t> s_gidx, s_var_off, s_var_copy, s_groups;
+    DevBuf<int4> s_ell;  // the first four copies of each variable
     DevBuf<double> s_part, s_x2;
     hipGraph_t s_graph = nullptr;
     hipGraphExec_t s_exec = nullptr;
@@ -80,6 +82,7 @@ struct ldopf_problem {
         for (DevBuf<uint16_t>* q : {&row_lvar, &row_sub, &var_copy_off, &var_copy_rows, &tk_sub}) q->ordered = s;
         parts.ordered = s;
         subs.ordered = s;
+        s_ell.ordered = s;
         var_writer.ordered = s;
         bpart.ordered = s;
         st.ordered = s;

@@ -44,6 +44,7 @@ struct StreamArgs {
     const int32_t* gidx;
     const int32_t* var_off;
     const int32_t* var_copy;
+    const int4* ell;  // per variable its first four copies, -1 padded
     const double* basis;
     const double* bbar;
     const double* c;
@@ -140,15 +141,37 @@ __device__ void stream_test(const StreamArgs& a, int rows) {
 }
 
 // closed_1: x_i = clip((sum_c x_s,c - (c_i + sum_c lambda_c) / rho) / N_i) over
-// the copies c of variable i, in copy order (a NaN passes the clip); block 0
-// first runs the test of the previous sweep.
+// the copies c of variable i, in copy order (a NaN passes the clip); the
+// first four copies come from a padded table, so that their loads are in
+// flight together, further ones from the CSR list. Block 0 runs the test of
+// the previous sweep instead, beside the update blocks; an update block that
+// sees the stop it decides skips its variables, which only spares the half
+// of x the returned sweep does not use.
 __global__ __launch_bounds__(256) void stream_global_kernel(StreamArgs a, int rows) {
     if (a.ctrl[1]) return;
-    if (blockIdx.x == 0) stream_test(a, rows);
-    const int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (blockIdx.x == 0) {
+        stream_test(a, rows);
+        return;
+    }
+    const int64_t v = int64_t(blockIdx.x - 1) * 256 + threadIdx.x;
     if (v >= a.n) return;
+    const int4 e = a.ell[v];
+    const int q0 = a.var_off[v], q1 = a.var_off[v + 1];
+    const int ec[4] = {e.x, e.y, e.z, e.w};
+    double xs4[4], lm4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        xs4[i] = ec[i] >= 0 ? a.xs[ec[i]] : 0.0;
+        lm4[i] = ec[i] >= 0 ? a.lam[ec[i]] : 0.0;
+    }
     double sx = 0.0, sl = 0.0;
-    for (int q = a.var_off[v]; q < a.var_off[v + 1]; ++q) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (q0 + i < q1) {
+            sx += xs4[i];
+            sl += lm4[i];
+        }
+    for (int q = q0 + 4; q < q1; ++q) {
         const int c = a.var_copy[q];
         sx += a.xs[c];
         sl += a.lam[c];
@@ -201,6 +224,44 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
                 v[q] = z[q] + l[q] * irho;
             }
         }
+        if constexpr (NQ == 1) {
+            // one row per lane: batches of kKB operator rows, the next batch
+            // issued before the current one is used. Rows past K_s or lanes
+            // past n_s read an address inside the operator (or the first
+            // basis word, for an idle lane or K_s = 0) and contribute zero:
+            // v is zero past n_s and t_k is masked past K_s, so every load
+            // is unconditional
+            const int Kc = K > 0 ? K : 1, nc = n > 0 ? n : 1;
+            const double* Wl = K > 0 ? W : a.basis;
+            const int jc = jl < nc ? jl : nc - 1;
+            auto issue = [&](double (&w)[kKB], int k0) {
+#pragma unroll
+                for (int kb = 0; kb < kKB; ++kb) {
+                    const int k = k0 + kb < Kc ? k0 + kb : Kc - 1;
+                    w[kb] = Wl[int64_t(k) * nc + jc];
+                }
+            };
+            auto use = [&](const double (&w)[kKB], int k0) {
+                double t[kKB];
+#pragma unroll
+                for (int kb = 0; kb < kKB; ++kb) t[kb] = w[kb] * v[0];
+                for (int m = G >> 1; m >= 1; m >>= 1)
+#pragma unroll
+                    for (int kb = 0; kb < kKB; ++kb) t[kb] += __shfl_xor(t[kb], m, 64);
+#pragma unroll
+                for (int kb = 0; kb < kKB; ++kb) acc[0] += w[kb] * (k0 + kb < K ? t[kb] : 0.0);
+            };
+            double wa[kKB], wb[kKB];
+            issue(wa, 0);
+            for (int k0 = 0;; k0 += 2 * kKB) {
+                issue(wb, k0 + kKB);
+                use(wa, k0);
+                if (k0 + kKB >= kmax) break;
+                issue(wa, k0 + 2 * kKB);
+                use(wb, k0 + kKB);
+                if (k0 + 2 * kKB >= kmax) break;
+            }
+        } else
         // all loads of a batch first, then its butterfly sums side by side
         for (int k0 = 0; k0 < kmax; k0 += kKB) {
             double w[kKB][NQ];
@@ -269,6 +330,7 @@ StreamArgs stream_args(ldopf_problem& h) {
     a.gidx = h.s_gidx.p;
     a.var_off = h.s_var_off.p;
     a.var_copy = h.s_var_copy.p;
+    a.ell = h.s_ell.p;
     a.basis = h.basis.p;
     a.bbar = h.bbar.p;
     a.c = h.c.p;
@@ -369,6 +431,13 @@ void stream_prepare(ldopf_problem& h) {
     h.s_gidx.upload(g32, s, "upload streamed plan");
     h.s_var_off.upload(var_off, s, "upload streamed plan");
     h.s_var_copy.upload(var_copy, s, "upload streamed plan");
+    std::vector<int4> ell(lp.n);
+    for (int64_t v = 0; v < lp.n; ++v) {
+        int32_t e[4] = {-1, -1, -1, -1};
+        for (int32_t i = 0; i < 4 && var_off[v] + i < var_off[v + 1]; ++i) e[i] = var_copy[var_off[v] + i];
+        ell[v] = int4{e[0], e[1], e[2], e[3]};
+    }
+    h.s_ell.upload(ell, s, "upload streamed plan");
     h.s_part.alloc(size_t(kSBlocks) * 5, "streamed residual rows");
     h.s_x2.alloc(size_t(2) * lp.n, "streamed x halves");
     h.s_ctrl.alloc(2, "streamed control");
@@ -396,7 +465,7 @@ void stream_solve(ldopf_problem& h) {
     for (int i = 0; i < kSGraph; ++i) {
         StreamArgs ai = a;
         ai.x = a.x + int64_t((i + 1) % 2) * a.n;
-        hipLaunchKernelGGL(stream_global_kernel, dim3(std::max(gblocks, 1u)), dim3(256), 0, s, ai, rows);
+        hipLaunchKernelGGL(stream_global_kernel, dim3(gblocks + 1), dim3(256), 0, s, ai, rows);
         void* args[] = {&ai};
         (void)hipLaunchKernel(local_kernel(h.s_nq), dim3(rows), dim3(64 * kSWaves), args, 0, s);
     }
