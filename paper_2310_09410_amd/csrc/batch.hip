@@ -704,6 +704,8 @@ struct ldopf_batch {
     int32_t B = 0, Bp = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t* hctrl = nullptr;                 // pinned: the control words after two graphs
+    hipEvent_t evc[2] = {nullptr, nullptr};  // recorded after each of those reads
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t graph_sweeps = 16;
@@ -730,6 +732,9 @@ struct ldopf_batch {
         if (graph) (void)hipGraphDestroy(graph);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        for (hipEvent_t e : evc)
+            if (e) (void)hipEventDestroy(e);
+        if (hctrl) (void)hipHostFree(hctrl);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -884,14 +889,30 @@ int64_t run_to_done(ldopf_batch& h, double* ms_out) {
     hip_check(hipMemcpyAsync(ctrl, h.ctrl.p, sizeof(ctrl), hipMemcpyDeviceToHost, h.stream), "download control");
     hip_check(hipStreamSynchronize(h.stream), "download control");
     hip_check(hipEventRecord(h.ev0, h.stream), "event");
-    for (;;) {
-        const int64_t before = ctrl[0];
+    // Each graph is followed by a read of the control words into pinned
+    // memory and an event; the next graph is queued before the host waits
+    // for the last one's words, so the host's round trip overlaps sweeps (a
+    // graph queued after the stop returns at once).
+    int64_t* hc = h.hctrl;
+    auto queue = [&](int b) {
         hip_check(hipGraphLaunch(h.exec, h.stream), "graph launch");
-        hip_check(hipMemcpyAsync(ctrl, h.ctrl.p, sizeof(ctrl), hipMemcpyDeviceToHost, h.stream), "download control");
-        hip_check(hipStreamSynchronize(h.stream), "batch sweep");
+        hip_check(hipMemcpyAsync(hc + 2 * b, h.ctrl.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, h.stream),
+                  "download control");
+        hip_check(hipEventRecord(h.evc[b], h.stream), "event");
+    };
+    int b = 0;
+    int64_t before = ctrl[0];
+    queue(0);
+    for (;;) {
+        queue(b ^ 1);
+        hip_check(hipEventSynchronize(h.evc[b]), "batch sweep");
+        ctrl[0] = hc[2 * b];
+        ctrl[1] = hc[2 * b + 1];
         if (ctrl[1]) break;
         // every sweep of a graph that did not finish the batch advances the count
         if (ctrl[0] != before + h.graph_sweeps) fail(LDOPF_DEVICE_ERROR, "the batched sweep count did not advance");
+        before = ctrl[0];
+        b ^= 1;
     }
     hip_check(hipEventRecord(h.ev1, h.stream), "event");
     hip_check(hipEventSynchronize(h.ev1), "event");
@@ -970,6 +991,9 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             hip_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "stream");
             hip_check(hipEventCreate(&h->ev0), "event");
             hip_check(hipEventCreate(&h->ev1), "event");
+            for (hipEvent_t& e : h->evc) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+            hip_check(hipHostMalloc(reinterpret_cast<void**>(&h->hctrl), 4 * sizeof(int64_t), hipHostMallocDefault),
+                      "pinned control");
             if (stream) {
                 // order after the caller's pending work
                 hipEvent_t e;

@@ -68,6 +68,8 @@ struct ldopf_problem {
     DevBuf<double> s_part, s_x2;
     hipGraph_t s_graph = nullptr;
     hipGraphExec_t s_exec = nullptr;
+    int64_t* s_hctrl = nullptr;                 // pinned: the control words after two graphs
+    hipEvent_t s_evc[2] = {nullptr, nullptr};  // recorded after each of those reads
 
     // every device buffer allocated and released in order on `s` (the
     // serving runtime's slot streams, which outlive their problems)
@@ -92,6 +94,9 @@ struct ldopf_problem {
         if (stream) (void)hipStreamSynchronize(stream);
         if (s_exec) (void)hipGraphExecDestroy(s_exec);
         if (s_graph) (void)hipGraphDestroy(s_graph);
+        if (s_hctrl) (void)hipHostFree(s_hctrl);
+        for (hipEvent_t e : s_evc)
+            if (e) (void)hipEventDestroy(e);
         if (own_pinned && last_pinned) (void)hipHostFree(last_pinned);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);

@@ -441,6 +441,11 @@ void stream_prepare(ldopf_problem& h) {
     h.s_part.alloc(size_t(kSBlocks) * 5, "streamed residual rows");
     h.s_x2.alloc(size_t(2) * lp.n, "streamed x halves");
     h.s_ctrl.alloc(2, "streamed control");
+    if (!h.s_hctrl)
+        hip_check(hipHostMalloc(reinterpret_cast<void**>(&h.s_hctrl), 4 * sizeof(int64_t), hipHostMallocDefault),
+                  "pinned control");
+    for (hipEvent_t& e : h.s_evc)
+        if (!e) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
     h.s_nq = max_n <= 64 ? 1 : (max_n <= 256 ? 4 : 16);
     h.streamed = true;
     h.plan = Plan{};
@@ -471,19 +476,34 @@ void stream_solve(ldopf_problem& h) {
     }
     hip_check(hipStreamEndCapture(s, &h.s_graph), "graph capture");
     hip_check(hipGraphInstantiate(&h.s_exec, h.s_graph, nullptr, nullptr, 0), "graph instantiate");
-    int64_t ctrl[2] = {0, 0};
-    for (;;) {
-        const int64_t before = ctrl[0];
+    // Each graph is followed by a read of the control words into pinned
+    // memory and an event; the next graph is queued before the host waits
+    // for the last one's words, so the host's round trip overlaps sweeps (a
+    // graph queued after the stop returns at once).
+    int64_t* hc = h.s_hctrl;
+    auto queue = [&](int b) {
         hip_check(hipGraphLaunch(h.s_exec, s), "graph launch");
-        hip_check(hipMemcpyAsync(ctrl, h.s_ctrl.p, sizeof(ctrl), hipMemcpyDeviceToHost, s), "download control");
-        hip_check(hipStreamSynchronize(s), "streamed sweep");
-        if (ctrl[1]) break;
+        hip_check(hipMemcpyAsync(hc + 2 * b, h.s_ctrl.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s),
+                  "download control");
+        hip_check(hipEventRecord(h.s_evc[b], s), "event");
+    };
+    int b = 0;
+    int64_t before = 0, t = 0;
+    queue(0);
+    for (;;) {
+        queue(b ^ 1);
+        hip_check(hipEventSynchronize(h.s_evc[b]), "streamed sweep");
+        t = hc[2 * b];
+        if (hc[2 * b + 1]) break;
         // every sweep of a graph that did not stop advances the count
-        if (ctrl[0] != before + kSGraph) fail(LDOPF_DEVICE_ERROR, "the streamed sweep count did not advance");
+        if (t != before + kSGraph) fail(LDOPF_DEVICE_ERROR, "the streamed sweep count did not advance");
+        before = t;
+        b ^= 1;
     }
-    // the x of the returned sweep (ctrl[0] when stopped) into the handle's x
-    if (ctrl[0] >= 1)
-        hip_check(hipMemcpyAsync(h.x.p, h.s_x2.p + (ctrl[0] % 2) * a.n, size_t(a.n) * 8, hipMemcpyDeviceToDevice, s),
+    // the x of the returned sweep (the sweep number when stopped) into the
+    // handle's x, after the graph queued last
+    if (t >= 1)
+        hip_check(hipMemcpyAsync(h.x.p, h.s_x2.p + (t % 2) * a.n, size_t(a.n) * 8, hipMemcpyDeviceToDevice, s),
                   "copy x");
 }
 
