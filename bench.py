@@ -335,6 +335,30 @@ def run_small(P, L, make_feeder, stream, steps: int = 5) -> dict:
     return out
 
 
+def exchange_floor(P, make_feeder, stream, sweeps: int = 20000) -> dict:
+    """Time per sweep with the neighbour exchange and the grid-wide test over
+    many workgroups but little work in each (fixed sweeps, FP64): the
+    123-bus feeder cut into about 24 copies per workgroup (186 workgroups,
+    one per subsystem), and the 2500-bus feeder on 256 workgroups of about 220
+    copies; beside the 8500-bus sweep (256 workgroups of about 700 copies) and
+    the 13-bus sweep (one workgroup, no exchange), they show how much of a
+    sweep is the exchange floor and how much the work of a part."""
+    out = {}
+    for name, rows in (("123", 16), ("2500", 1)):
+        net = make_feeder(name, int(name))
+        prob = P.ldopf_create(net, P.ldopf_default_options(max_iter=sweeps, check_termination=0, rows_per_part=rows),
+                              stream=stream)
+        prob.solve()
+        prob.reset()
+        st = prob.solve()
+        sz = prob.sizes()
+        out[f"{name}bus"] = {"workgroups": sz.n_parts, "block_threads": sz.block_threads,
+                             "local_copies_per_workgroup": sz.n_local / max(1, sz.n_parts),
+                             "us_per_sweep": 1e3 * st.sweep_ms / max(1, st.sweeps_computed)}
+        prob.close()
+    return out
+
+
 def phase_profile(P, net, stream, sweeps: int = 20000) -> dict:
     """Per-phase wall-clock time of one workgroup of the 8500-bus sweep
     (profiled build of the kernel, fixed sweeps), in us per sweep."""
@@ -508,6 +532,7 @@ def main():
         rec["small_feeders"] = run_small(P, L, make_feeder, stream)
         rec["sync_floor"] = {"us_per_sweep_13bus_one_workgroup": rec["small_feeders"]["13"]["us_per_sweep"],
                              "us_per_sweep_8500bus": rec["us_per_sweep"],
+                             "many_workgroups_little_work": exchange_floor(P, make_feeder, stream),
                              "phase_us_8500bus_workgroup0": phase_profile(P, net, stream)}
         progress("small feeders and phase profile done")
     if not args.no_fp32:
