@@ -118,10 +118,11 @@ typedef enum ldopf_sweep_path {
      * fit */
     LDOPF_PATH_PERSISTENT = 1,
     /* the streamed sweep: the same steps of Algorithm 1 with the operators
-     * and state in HBM, three launches per sweep (global update; local and
-     * dual update with the residual sums of each block; the sums in a fixed
-     * order and the test), captured in HIP graphs and replayed by the host
-     * until the test holds. FP64 only, literal residual form and fixed rho;
+     * and state in HBM, two launches per sweep (global update, beside it
+     * the test of the previous sweep on the residual sums of its blocks in a
+     * fixed order; local and dual update with the residual sums of each
+     * block), captured in HIP graphs and replayed by the host until the test
+     * holds. FP64 only, literal residual form and fixed rho;
      * not for ldopf_solve_noalloc, ldopf_solve_many or the server (those
      * calls return LDOPF_UNSUPPORTED for such a problem) */
     LDOPF_PATH_STREAMED = 2

@@ -1,4 +1,4 @@
-"""GPU parity of the streamed sweep (operators and state in HBM, three
+"""GPU parity of the streamed sweep (operators and state in HBM, two
 launches per sweep, graphs replayed by the host) against the FP64 oracle.
 
 The streamed sweep is the path for problems whose operators and state do not
