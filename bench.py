@@ -78,8 +78,9 @@ def stored_traffic():
 
 def batched_bytes_per_sweep(bs) -> float:
     """Compulsory bytes of one batched sweep (FP32): shared and per-scenario
-    operators once, and per scenario bbar, x_s and lambda read and written,
-    the gather of B_s x and the global x written."""
+    operators once, and per scenario bbar, x_s and lambda read and written
+    (stored as x_s - lambda / rho and lambda), the gather of B_s x and the
+    global x written."""
     per_scen = 4 * (bs.n_local * (1 + 4 + 1) + bs.n)
     return 4 * (bs.shared_operator_words + bs.scenario_operator_words) + bs.n_scen * per_scen
 

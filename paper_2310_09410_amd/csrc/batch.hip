@@ -29,6 +29,12 @@
 //
 // State layout in HBM: row-major [copy or variable][scenario], scenarios
 // padded to Bp (a multiple of 64), so a wave reads 64 consecutive scenarios.
+// Each copy keeps lambda and u = x_s - lambda / rho instead of x_s: the
+// global update needs only the sum of u over a variable's copies (one word
+// per copy instead of two), and the local update forms the previous x_s =
+// u + lambda / rho for the dual residual (the same FP32 arithmetic gives the
+// same x; the reconstructed x_s differs from the computed one by the FP32
+// rounding of the subtraction).
 
 #include <hip/hip_runtime.h>
 
@@ -144,7 +150,7 @@ struct BatchArgs {
     const float* hi;
     const float* invN;
     float* X;  // the half of the two-part x buffer this sweep writes (global) and reads (local)
-    float* XS;
+    float* U;  // per copy and scenario: u = x_s - lambda / rho (so x_s = u + lambda / rho)
     float* LAM;
     const float* BB;
     const int4* ell;      // [n] first four copies of each variable, -1 padded
@@ -356,33 +362,27 @@ __global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
     if (tile * kTile >= a.Bp) return;
     const int sc = tile * kTile + lane;
     if (v0 >= a.n || !a.active[sc]) return;
-    const float irho = float(1.0 / a.rho);
     const int64_t Bp = a.Bp;
-    float xs[kVPW][4], lm[kVPW][4];
+    // the copies' x_s - lambda / rho, as the local update left them
+    float uc[kVPW][4];
 #pragma unroll
     for (int u = 0; u < kVPW; ++u) {
         const int64_t v = v0 + u;
         const int4 e = v < a.n ? a.ell[v] : int4{-1, -1, -1, -1};
         const int ec[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            xs[u][i] = ec[i] >= 0 ? a.XS[int64_t(ec[i]) * Bp + sc] : 0.f;
-            lm[u][i] = ec[i] >= 0 ? a.LAM[int64_t(ec[i]) * Bp + sc] : 0.f;
-        }
+        for (int i = 0; i < 4; ++i) uc[u][i] = ec[i] >= 0 ? a.U[int64_t(ec[i]) * Bp + sc] : 0.f;
     }
 #pragma unroll
     for (int u = 0; u < kVPW; ++u) {
         const int64_t v = v0 + u;
         if (v >= a.n) break;
         const int q0 = a.var_off[v], q1 = a.var_off[v + 1];
-        float s = xs[u][0] - lm[u][0] * irho;
+        float s = uc[u][0];
 #pragma unroll
         for (int i = 1; i < 4; ++i)
-            if (q0 + i < q1) s += xs[u][i] - lm[u][i] * irho;
-        for (int q = q0 + 4; q < q1; ++q) {
-            const int64_t c = a.var_copy[q];
-            s += a.XS[c * Bp + sc] - a.LAM[c * Bp + sc] * irho;
-        }
+            if (q0 + i < q1) s += uc[u][i];
+        for (int q = q0 + 4; q < q1; ++q) s += a.U[int64_t(a.var_copy[q]) * Bp + sc];
         float x = (s - a.crho[v]) * a.invN[v];
         x = x < a.lo[v] ? a.lo[v] : x;
         x = x > a.hi[v] ? a.hi[v] : x;
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
 
 // Local + dual update of both classes, four waves per block on one
 // 64-scenario tile (lane = scenario). Rows j of a subsystem belong to wave
-// j % 4; a wave keeps its rows' z, lambda and old x_s in registers (at most
+// j % 4; a wave keeps its rows' z, lambda and old u in registers (at most
 // RPW rows, so n_s <= 4 RPW) and stages v = z + lambda / rho and bbar, then
 // the projection y, in LDS ([row][kZS], kZS = 80 floats: rows four apart fall on
 // disjoint halves of the 32 banks, so the MFMA operand reads do not
@@ -404,7 +404,8 @@ __global__ __launch_bounds__(256) void batch_global_kernel(BatchArgs a) {
 //     B[l / 16][l % 16] and D[4 (l / 16) + i][l % 16], i < 4;
 //   per-scenario class: t = W v (wave w takes basis rows w, w + 4, ...), then
 //     y = bbar + v - W't (mode 1) or bbar + W't (mode 0) per row.
-// Then lambda += rho (z - y), and the FP64 residual sums per scenario.
+// Then lambda += rho (z - y), u = y - lambda / rho, and the FP64 residual
+// sums per scenario.
 // Four blocks per CU (four waves per SIMD, at most 128 VGPRs) for the common
 // subsystem width: the phases of a subsystem (row loads, MFMA or operator
 // streams, barriers) then overlap across blocks. The wider variants keep
@@ -452,7 +453,7 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
             const int n = m.n;
             const int64_t row0 = m.row0;
             const float* LAMb = a.LAM + row0 * Bp;
-            const float* XSb = a.XS + row0 * Bp;
+            const float* Ub = a.U + row0 * Bp;
             const float* BBb = a.BB + row0 * Bp;
             // row indices first, then every row load of the wave before any
             // use; rows past n_s repeat the last row (loaded, never used) so
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
                 const int o = min(wv + 4 * r, n - 1) * Bp + sc;
                 z[r] = a.X[gi[r] * Bp + sc];
                 l0[r] = LAMb[o];
-                xo[r] = XSb[o];
+                xo[r] = Ub[o];  // u of the previous sweep; x_s = u + lambda / rho
                 bb[r] = BBb[o];
             }
             float y[RPW];
@@ -630,7 +631,7 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
                 }
             }
             // dual update and residual sums on the wave's own rows
-            float* XSw = a.XS + row0 * Bp;
+            float* Uw = a.U + row0 * Bp;
             float* LAMw = a.LAM + row0 * Bp;
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
@@ -639,9 +640,10 @@ __global__ __launch_bounds__(256, RPW <= 10 ? 4 : 1) void batch_local_kernel(Bat
                     const int o = j * Bp + sc;
                     const float yj = y[r];
                     const float l1 = l0[r] + rho * (z[r] - yj);
-                    XSw[o] = yj;
+                    Uw[o] = yj - l1 * irho;
                     LAMw[o] = l1;
-                    const double dz = double(z[r]) - double(yj), dx = double(yj) - double(xo[r]);
+                    const float xprev = xo[r] + l0[r] * irho;
+                    const double dz = double(z[r]) - double(yj), dx = double(yj) - double(xprev);
                     p0 += dz * dz;
                     p1 += dx * dx;
                     p2 += double(z[r]) * double(z[r]);
@@ -676,7 +678,7 @@ __global__ void batch_init_kernel(BatchArgs a, const double* x_init) {
     const int64_t total = a.nloc * a.Bp;
     if (i < total) {
         const int64_t c = i / a.Bp;
-        a.XS[i] = float(x_init[a.gidx[c]]);
+        a.U[i] = float(x_init[a.gidx[c]]);  // lambda = 0: u = x_s
         a.LAM[i] = 0.f;
     }
     if (i < 2 * a.n * a.Bp) a.X[i] = 0.f;  // both halves
@@ -722,7 +724,7 @@ struct ldopf_batch {
     std::vector<LocalMeta> meta_h;  // per subsystem, in subsystem order
     DevBuf<int4> ell;
     DevBuf<int64_t> loc_off, wofs, iters, ctrl;
-    DevBuf<float> crho, lo, hi, invN, X, XS, LAM, BB, ash, W;
+    DevBuf<float> crho, lo, hi, invN, X, U, LAM, BB, ash, W;
     DevBuf<double> x_init, part, part2, res;
     DevBuf<int32_t> active, conv, sflags, tick;
 
@@ -757,7 +759,7 @@ BatchArgs batch_args(ldopf_batch& h) {
     a.hi = h.hi.p;
     a.invN = h.invN.p;
     a.X = h.X.p;
-    a.XS = h.XS.p;
+    a.U = h.U.p;
     a.LAM = h.LAM.p;
     a.BB = h.BB.p;
     a.ell = h.ell.p;
@@ -1243,7 +1245,7 @@ int ldopf_batch_create(const ldopf_network* net, int32_t n_scen, const double* l
             h->invN.upload(invN, s, "upload counts");
             h->x_init.upload(L.x_init, s, "upload start");
             h->X.alloc(2 * size_t(L.n) * Bp, "x");
-            h->XS.alloc(size_t(nloc) * Bp, "x_s");
+            h->U.alloc(size_t(nloc) * Bp, "x_s - lambda / rho");
             h->LAM.alloc(size_t(nloc) * Bp, "lambda");
             h->active.alloc(Bp, "masks");
             h->conv.alloc(Bp, "masks");
@@ -1348,15 +1350,16 @@ int ldopf_batch_get_local(const ldopf_batch* h, int32_t scen, double* xs, double
         if (scen < 0 || scen >= h->B) fail(LDOPF_INVALID_ARGUMENT, "scenario out of range");
         const int64_t nl = int64_t(h->lp.gidx.size());
         if (cap < nl) fail(LDOPF_BUFFER_TOO_SMALL, "x_s and lambda need N_loc entries");
-        std::vector<float> col(nl);
+        std::vector<float> u(nl), l(nl);
+        hip_check(hipMemcpy2D(l.data(), 4, h->LAM.p + scen, size_t(h->Bp) * 4, 4, nl, hipMemcpyDeviceToHost), "download lambda");
         if (xs) {
-            hip_check(hipMemcpy2D(col.data(), 4, h->XS.p + scen, size_t(h->Bp) * 4, 4, nl, hipMemcpyDeviceToHost), "download x_s");
-            for (int64_t c = 0; c < nl; ++c) xs[c] = col[c];
+            // x_s = u + lambda / rho, formed as the local update forms it
+            hip_check(hipMemcpy2D(u.data(), 4, h->U.p + scen, size_t(h->Bp) * 4, 4, nl, hipMemcpyDeviceToHost), "download x_s");
+            const float irho = float(1.0 / h->opts.rho);
+            for (int64_t c = 0; c < nl; ++c) xs[c] = double(u[c] + l[c] * irho);
         }
-        if (lam) {
-            hip_check(hipMemcpy2D(col.data(), 4, h->LAM.p + scen, size_t(h->Bp) * 4, 4, nl, hipMemcpyDeviceToHost), "download lambda");
-            for (int64_t c = 0; c < nl; ++c) lam[c] = col[c];
-        }
+        if (lam)
+            for (int64_t c = 0; c < nl; ++c) lam[c] = l[c];
     });
 }
 
