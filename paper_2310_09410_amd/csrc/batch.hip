@@ -61,7 +61,7 @@ namespace {
 
 constexpr int kTile = 64;  // scenarios per wave
 constexpr int kZS = 80;    // LDS row stride (floats) of the local update
-constexpr int kVPW = 4;    // variables per wave in the global update
+constexpr int kVPW = 8;    // variables per wave in the global update
 constexpr int kRedBlocks = 16;  // reduction blocks (four waves each) per scenario tile
 constexpr int kKB = 1;         // operator rows per load batch of the per-scenario class
 
