@@ -6,14 +6,15 @@
 // update ADMM-3, the residual sums and the test of Section III-C), with every
 // operand in HBM and one launch per step: the global update (a thread per
 // variable, its copies from a CSR list), the local and dual update (a wave
-// per subsystem, a lane per row: t_k = sum_j W_kj v_j by a butterfly sum over
-// the wave, then y_j = bbar_j + v_j - sum_k W_kj t_k in mode 1 or bbar_j +
-// sum_k W_kj t_k in mode 0, with W the K_s rows of the precomputed basis that
-// span the smaller of the row space and its complement), and the test of
-// Section III-C, which block 0 of the next global update runs on the local
-// update's per-block residual sums, in a fixed order. The global update of
-// sweep k writes x into the half k % 2 of a two-part buffer, so the x of
-// the sweep that passed the test survives the next sweep's global update.
+// per subsystem, a lane per row: t_k = sum_j W_kj v_j by a sum over the
+// subsystem's lanes, then y_j = bbar_j + v_j - sum_k W_kj t_k in mode 1 or
+// bbar_j + sum_k W_kj t_k in mode 0, with W the K_s rows of the precomputed
+// basis that span the smaller of the row space and its complement), and the
+// test of Section III-C, which block 0 of the next global update runs on the
+// local update's per-block residual sums, in a fixed order. The global
+// update of sweep k writes x into the half k % 2 of a two-part buffer, so the
+// x of the sweep that passed the test survives the next sweep's global
+// update.
 // A launch after the stop returns at once, so C sweeps are captured in one
 // HIP graph and the host replays it until the test holds. FP64 throughout;
 // the returned state is that of the sweep that passed the test.
@@ -64,10 +65,36 @@ struct StreamArgs {
     int32_t check;
 };
 
-__device__ inline double wave_sum(double v) {
-    // xor butterfly: every lane ends with the same bits
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+// DPP lane moves inside each row of 16 lanes (gfx9 encodings): quad_perm
+// [1,0,3,2] swaps neighbours, quad_perm [2,3,0,1] swaps pairs,
+// row_half_mirror reverses each group of 8, row_mirror each row of 16.
+template <int CTRL>
+__device__ inline double row_move(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sums of kKB values over aligned groups of G lanes (G = 16, 32 or 64), the
+// kKB chains side by side; every lane of a group ends with the same bits:
+// within each row of 16 by DPP moves, across rows by lane exchanges. Every
+// lane of the wave must be active.
+template <int N>
+__device__ inline void group_sums(double (&t)[N], int G) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] += row_move<0xB1>(t[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] += row_move<0x4E>(t[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] += row_move<0x141>(t[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] += row_move<0x140>(t[i]);
+    if (G >= 32)
+#pragma unroll
+        for (int i = 0; i < N; ++i) t[i] += __shfl_xor(t[i], 16, 64);
+    if (G >= 64)
+#pragma unroll
+        for (int i = 0; i < N; ++i) t[i] += __shfl_xor(t[i], 32, 64);
 }
 
 __global__ void stream_init_kernel(StreamArgs a) {
@@ -86,7 +113,7 @@ __global__ void stream_init_kernel(StreamArgs a) {
 
 // Block 0 of a global update: the test of the sweep whose local update ran
 // last (its blocks' residual rows in a fixed order: thread r takes rows r,
-// r + 256, ..., then butterfly sums over each wave and the waves in order),
+// r + 256, ..., then sums over each wave and the waves in order),
 // its history row and status; then either the stop or the next sweep's
 // number. Every thread of the block calls it.
 __device__ void stream_test(const StreamArgs& a, int rows) {
@@ -98,8 +125,7 @@ __device__ void stream_test(const StreamArgs& a, int rows) {
         for (int r = threadIdx.x; r < rows; r += 256)
 #pragma unroll
             for (int q = 0; q < 5; ++q) p[q] += a.part[int64_t(r) * 5 + q];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) p[q] = wave_sum(p[q]);
+        group_sums(p, 64);
         if (lane == 0)
 #pragma unroll
             for (int q = 0; q < 5; ++q) red[wv][q] = p[q];
@@ -184,7 +210,7 @@ __global__ __launch_bounds__(256) void stream_global_kernel(StreamArgs a, int ro
 // closed_2, ADMM-3 and the residual sums. A wave takes one group of
 // subsystems at a time: four of at most 16 variables (16 lanes each), two of
 // at most 32, or one (64 lanes, NQ rows per lane, n_s <= 64 NQ); a lane holds
-// row j of its subsystem, and t_k is a butterfly sum over the subsystem's
+// row j of its subsystem, and t_k is a sum over the subsystem's
 // lanes. Operator rows are loaded kKB at a time (fewer for more rows per
 // lane, so that the batch stays in registers).
 template <int NQ>
@@ -245,9 +271,7 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
                 double t[kKB];
 #pragma unroll
                 for (int kb = 0; kb < kKB; ++kb) t[kb] = w[kb] * v[0];
-                for (int m = G >> 1; m >= 1; m >>= 1)
-#pragma unroll
-                    for (int kb = 0; kb < kKB; ++kb) t[kb] += __shfl_xor(t[kb], m, 64);
+                group_sums(t, G);
 #pragma unroll
                 for (int kb = 0; kb < kKB; ++kb) acc[0] += w[kb] * (k0 + kb < K ? t[kb] : 0.0);
             };
@@ -262,7 +286,7 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
                 if (k0 + 2 * kKB >= kmax) break;
             }
         } else
-        // all loads of a batch first, then its butterfly sums side by side
+        // all loads of a batch first, then its lane-group sums side by side
         for (int k0 = 0; k0 < kmax; k0 += kKB) {
             double w[kKB][NQ];
 #pragma unroll
@@ -279,9 +303,7 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) t[kb] += w[kb][q] * v[q];
             }
-            for (int m = G >> 1; m >= 1; m >>= 1)
-#pragma unroll
-                for (int kb = 0; kb < kKB; ++kb) t[kb] += __shfl_xor(t[kb], m, 64);
+            group_sums(t, G);
 #pragma unroll
             for (int kb = 0; kb < kKB; ++kb)
 #pragma unroll
@@ -305,9 +327,8 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
             }
         }
     }
-    // the wave's sums (butterfly), then the waves in order
-#pragma unroll
-    for (int q = 0; q < 5; ++q) p[q] = wave_sum(p[q]);
+    // the wave's sums, then the waves in order
+    group_sums(p, 64);
     if (lane == 0)
 #pragma unroll
         for (int q = 0; q < 5; ++q) red[wv][q] = p[q];
