@@ -74,11 +74,13 @@ def test_batch_converged_matches_oracle(gpu, name):
     assert sum(g > 0.02 for g in gaps) <= 1, gaps
 
 
-def test_batch_fixed_sweeps_match_oracle(gpu):
+@pytest.mark.parametrize("T", [150, 37])
+def test_batch_fixed_sweeps_match_oracle(gpu, T):
+    """After T sweeps (an even and an odd count: x of sweep k is kept in the
+    half k % 2 of a two-part buffer), every scenario against the oracle."""
     P = gpu
     net = feeder("123")
     f = _factors(net, 5, 31)
-    T = 150
     b = P.ldopf_batch_create(net, f, P.ldopf_default_options(precision=1, max_iter=T, check_termination=0))
     st = b.solve()
     assert st.sweeps == T

@@ -29,7 +29,7 @@ def _big_feeder():
     return make_feeder(dataclasses.replace(SPECS["8500"], n_bus=12000), 12000)
 
 
-@pytest.mark.parametrize("name,T", [("13", 200), ("123", 100), ("2500", 30)])
+@pytest.mark.parametrize("name,T", [("13", 200), ("123", 100), ("123", 37), ("2500", 30)])
 def test_streamed_fixed_sweeps(gpu, name, T):
     from oracle import admm
     P = gpu
