@@ -4,17 +4,20 @@
 // The same sweep as the persistent kernel (Algorithm 1: global update of
 // closed_1 in its derived form, local update of closed_2 in rank form, dual
 // update ADMM-3, the residual sums and the test of Section III-C), with every
-// operand in HBM and one launch per step: the global update (a thread per
-// variable, its copies from a CSR list), the local and dual update (a wave
-// per subsystem, a lane per row: t_k = sum_j W_kj v_j by a sum over the
-// subsystem's lanes, then y_j = bbar_j + v_j - sum_k W_kj t_k in mode 1 or
-// bbar_j + sum_k W_kj t_k in mode 0, with W the K_s rows of the precomputed
-// basis that span the smaller of the row space and its complement), and the
-// test of Section III-C, which block 0 of the next global update runs on the
-// local update's per-block residual sums, in a fixed order. The global
-// update of sweep k writes x into the half k % 2 of a two-part buffer, so the
-// x of the sweep that passed the test survives the next sweep's global
-// update.
+// operand in HBM and one launch per sweep: a wave takes a group of
+// subsystems, a lane a row, and forms the global update of that row's
+// variable from the previous sweep's copies (closed_1: their x_s and lambda
+// over a padded table of the first four copies and a CSR list), then t_k =
+// sum_j W_kj v_j by a sum over the subsystem's lanes, y_j = bbar_j + v_j -
+// sum_k W_kj t_k in mode 1 or bbar_j + sum_k W_kj t_k in mode 0 (W the K_s
+// rows of the precomputed basis that span the smaller of the row space and
+// its complement), the dual update and the residual sums of its block. Block 0
+// of each launch instead runs the test of Section III-C on the previous
+// launch's block sums, in a fixed order, and stops the solve or numbers the
+// sweep. Sweep k reads x_s and lambda of sweep k - 1 and writes its own into
+// the other of two buffers (sweep k in buffer k % 2), its block sums and x
+// likewise, so a launch never reads what it writes, and the state of the
+// sweep that passed the test survives the launch that runs beside the test.
 // A launch after the stop returns at once, so C sweeps are captured in one
 // HIP graph and the host replays it until the test holds. FP64 throughout;
 // the returned state is that of the sweep that passed the test.
@@ -33,8 +36,8 @@ namespace ldopf {
 
 namespace {
 
-constexpr int kSWaves = 8;    // waves per block of the local update
-constexpr int kSBlocks = 1024; // blocks of the local update: rows of partial sums
+constexpr int kSWaves = 8;    // waves per block
+constexpr int kSBlocks = 1024; // blocks of subsystem groups per launch: rows of partial sums
 constexpr int kSGraph = 32;   // sweeps per captured graph
 
 struct StreamArgs {
@@ -52,11 +55,14 @@ struct StreamArgs {
     const double* lo;
     const double* hi;
     const double* cnt;
-    double* x;  // the half of the two-part x buffer this sweep writes (global) or reads (local)
-    double* xs;
-    double* lam;
-    double* part;  // [kSBlocks][5]
-    int64_t* ctrl; // [0] the sweep being computed (tested at the next global update), [1] stopped
+    double* x;              // the half of the two-part x buffer this sweep writes
+    const double* xs_rd;    // x_s and lambda of the previous sweep
+    const double* lam_rd;
+    double* xs_wr;          // x_s and lambda of this sweep (sweep k in buffer k % 2)
+    double* lam_wr;
+    const double* part_rd;  // block sums of the previous sweep [kSBlocks][5], tested here
+    double* part_wr;        // block sums of this sweep
+    int64_t* ctrl; // [0] the sweep being computed (tested by the next launch), [1] stopped
     double* hist;
     int64_t hist_cap;
     SweepStatus* st;
@@ -111,20 +117,20 @@ __global__ void stream_init_kernel(StreamArgs a) {
     st->rho_changes = 0;
 }
 
-// Block 0 of a global update: the test of the sweep whose local update ran
-// last (its blocks' residual rows in a fixed order: thread r takes rows r,
-// r + 256, ..., then sums over each wave and the waves in order),
-// its history row and status; then either the stop or the next sweep's
-// number. Every thread of the block calls it.
+// Block 0 of a launch: the test of the sweep the previous launch computed
+// (its blocks' residual rows in a fixed order: thread r takes rows r,
+// r + 512, ..., then sums over each wave and the waves in order), its
+// history row and status; then either the stop or the next sweep's number.
+// Every thread of the block calls it.
 __device__ void stream_test(const StreamArgs& a, int rows) {
-    __shared__ double red[4][5];
+    __shared__ double red[kSWaves][5];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t t = a.ctrl[0];
     if (t >= 1) {
         double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int r = threadIdx.x; r < rows; r += 256)
+        for (int r = threadIdx.x; r < rows; r += 64 * kSWaves)
 #pragma unroll
-            for (int q = 0; q < 5; ++q) p[q] += a.part[int64_t(r) * 5 + q];
+            for (int q = 0; q < 5; ++q) p[q] += a.part_rd[int64_t(r) * 5 + q];
         group_sums(p, 64);
         if (lane == 0)
 #pragma unroll
@@ -137,7 +143,10 @@ __device__ void stream_test(const StreamArgs& a, int rows) {
         return;
     }
     double d[5];
-    for (int q = 0; q < 5; ++q) d[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    for (int q = 0; q < 5; ++q) {
+        d[q] = 0.0;
+        for (int w = 0; w < kSWaves; ++w) d[q] += red[w][q];
+    }
     const double sq = sqrt(double(a.nloc));
     const double pres = sqrt(d[0]), dres = a.rho * sqrt(d[1]);
     const double eps_p = sq * a.eps_abs + a.eps_rel * fmax(sqrt(d[2]), sqrt(d[3]));
@@ -166,29 +175,19 @@ __device__ void stream_test(const StreamArgs& a, int rows) {
         a.ctrl[0] = t + 1;
 }
 
-// closed_1: x_i = clip((sum_c x_s,c - (c_i + sum_c lambda_c) / rho) / N_i) over
-// the copies c of variable i, in copy order (a NaN passes the clip); the
-// first four copies come from a padded table, so that their loads are in
-// flight together, further ones from the CSR list. Block 0 runs the test of
-// the previous sweep instead, beside the update blocks; an update block that
-// sees the stop it decides skips its variables, which only spares the half
-// of x the returned sweep does not use.
-__global__ __launch_bounds__(256) void stream_global_kernel(StreamArgs a, int rows) {
-    if (a.ctrl[1]) return;
-    if (blockIdx.x == 0) {
-        stream_test(a, rows);
-        return;
-    }
-    const int64_t v = int64_t(blockIdx.x - 1) * 256 + threadIdx.x;
-    if (v >= a.n) return;
+// closed_1 for variable v: x_v = clip((sum_c x_s,c - (c_v + sum_c lambda_c) /
+// rho) / N_v) over the copies c of v in the previous sweep, in copy order (a
+// NaN passes the clip); the first four copies come from a padded table, so
+// that their loads are in flight together, further ones from the CSR list.
+__device__ inline double global_x(const StreamArgs& a, int v) {
     const int4 e = a.ell[v];
     const int q0 = a.var_off[v], q1 = a.var_off[v + 1];
     const int ec[4] = {e.x, e.y, e.z, e.w};
     double xs4[4], lm4[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        xs4[i] = ec[i] >= 0 ? a.xs[ec[i]] : 0.0;
-        lm4[i] = ec[i] >= 0 ? a.lam[ec[i]] : 0.0;
+        xs4[i] = ec[i] >= 0 ? a.xs_rd[ec[i]] : 0.0;
+        lm4[i] = ec[i] >= 0 ? a.lam_rd[ec[i]] : 0.0;
     }
     double sx = 0.0, sl = 0.0;
 #pragma unroll
@@ -199,29 +198,38 @@ __global__ __launch_bounds__(256) void stream_global_kernel(StreamArgs a, int ro
         }
     for (int q = q0 + 4; q < q1; ++q) {
         const int c = a.var_copy[q];
-        sx += a.xs[c];
-        sl += a.lam[c];
+        sx += a.xs_rd[c];
+        sl += a.lam_rd[c];
     }
     const double xh = (sx - (a.c[v] + sl) / a.rho) / a.cnt[v];
     const double lo = a.lo[v], hi = a.hi[v];
-    a.x[v] = xh < lo ? lo : (xh > hi ? hi : xh);
+    return xh < lo ? lo : (xh > hi ? hi : xh);
 }
 
-// closed_2, ADMM-3 and the residual sums. A wave takes one group of
-// subsystems at a time: four of at most 16 variables (16 lanes each), two of
-// at most 32, or one (64 lanes, NQ rows per lane, n_s <= 64 NQ); a lane holds
-// row j of its subsystem, and t_k is a sum over the subsystem's
-// lanes. Operator rows are loaded kKB at a time (fewer for more rows per
-// lane, so that the batch stays in registers).
+// One sweep: closed_1 for each row's variable, closed_2, ADMM-3 and the
+// residual sums. A wave takes one group of subsystems at a time: four of at
+// most 16 variables (16 lanes each), two of at most 32, or one (64 lanes, NQ
+// rows per lane, n_s <= 64 NQ); a lane holds row j of its subsystem, forms
+// x of the row's variable (each copy's lane forms the same bits, and writes
+// them), and t_k is a sum over the subsystem's lanes. Operator rows are
+// loaded kKB at a time (fewer for more rows per lane, so that the batch
+// stays in registers). Block 0 runs the test of the previous sweep instead;
+// a block that sees the stop it decides skips its groups, which only spares
+// buffers the returned sweep does not use.
 template <int NQ>
-__global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a) {
+__global__ __launch_bounds__(64 * kSWaves) void stream_sweep_kernel(StreamArgs a, int rows) {
     constexpr int kKB = NQ >= 16 ? 1 : 2;
     if (a.ctrl[1]) return;
+    if (blockIdx.x == 0) {
+        stream_test(a, rows);
+        return;
+    }
     __shared__ double red[kSWaves][5];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t blk = int64_t(blockIdx.x) - 1, nblk = int64_t(gridDim.x) - 1;
     const double rho = a.rho, irho = 1.0 / a.rho;
     double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t g = int64_t(blockIdx.x) * kSWaves + wv; g < a.n_groups; g += int64_t(gridDim.x) * kSWaves) {
+    for (int64_t g = blk * kSWaves + wv; g < a.n_groups; g += nblk * kSWaves) {
         const int32_t* gr = a.groups + 8 * g;
         const int G = gr[0], count = gr[1], kmax = gr[2];
         const int slot = lane / G, jl = lane - slot * G;
@@ -244,9 +252,11 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
             z[q] = l[q] = xo[q] = v[q] = acc[q] = 0.0;
             if (j < n) {
                 const int64_t c = row0 + j;
-                z[q] = a.x[a.gidx[c]];
-                l[q] = a.lam[c];
-                xo[q] = a.xs[c];
+                const int var = a.gidx[c];
+                z[q] = global_x(a, var);
+                a.x[var] = z[q];
+                l[q] = a.lam_rd[c];
+                xo[q] = a.xs_rd[c];
                 v[q] = z[q] + l[q] * irho;
             }
         }
@@ -316,8 +326,8 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
                 const int64_t c = row0 + j;
                 const double y = a.bbar[c] + (mode ? v[q] - acc[q] : acc[q]);
                 const double l1 = l[q] + rho * (z[q] - y);
-                a.xs[c] = y;
-                a.lam[c] = l1;
+                a.xs_wr[c] = y;
+                a.lam_wr[c] = l1;
                 const double dz = z[q] - y, dx = y - xo[q];
                 p[0] += dz * dz;
                 p[1] += dx * dx;
@@ -336,7 +346,7 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_local_kernel(StreamArgs a
     if (threadIdx.x < 5) {
         double t = 0.0;
         for (int w = 0; w < kSWaves; ++w) t += red[w][threadIdx.x];
-        a.part[int64_t(blockIdx.x) * 5 + threadIdx.x] = t;
+        a.part_wr[blk * 5 + threadIdx.x] = t;
     }
 }
 
@@ -358,10 +368,15 @@ StreamArgs stream_args(ldopf_problem& h) {
     a.lo = h.lo.p;
     a.hi = h.hi.p;
     a.cnt = h.cnt.p;
+    // sweep k reads buffer (k - 1) % 2 and writes buffer k % 2; buffer 0 is
+    // the handle's x_s and lambda (the initial point or a warm start)
     a.x = h.s_x2.p;
-    a.xs = h.xs.p;
-    a.lam = h.lam.p;
-    a.part = h.s_part.p;
+    a.xs_rd = h.xs.p;
+    a.lam_rd = h.lam.p;
+    a.xs_wr = h.s_xs2.p;
+    a.lam_wr = h.s_lam2.p;
+    a.part_rd = h.s_part.p;
+    a.part_wr = h.s_part.p + size_t(kSBlocks) * 5;
     a.ctrl = h.s_ctrl.p;
     a.hist = h.hist.p;
     a.hist_cap = h.opts.history ? int64_t(h.hist.count / 4) : 0;
@@ -374,11 +389,11 @@ StreamArgs stream_args(ldopf_problem& h) {
     return a;
 }
 
-const void* local_kernel(int nq) {
+const void* sweep_kernel_for(int nq) {
     switch (nq) {
-        case 1: return reinterpret_cast<const void*>(&stream_local_kernel<1>);
-        case 4: return reinterpret_cast<const void*>(&stream_local_kernel<4>);
-        default: return reinterpret_cast<const void*>(&stream_local_kernel<16>);
+        case 1: return reinterpret_cast<const void*>(&stream_sweep_kernel<1>);
+        case 4: return reinterpret_cast<const void*>(&stream_sweep_kernel<4>);
+        default: return reinterpret_cast<const void*>(&stream_sweep_kernel<16>);
     }
 }
 
@@ -459,7 +474,9 @@ void stream_prepare(ldopf_problem& h) {
         ell[v] = int4{e[0], e[1], e[2], e[3]};
     }
     h.s_ell.upload(ell, s, "upload streamed plan");
-    h.s_part.alloc(size_t(kSBlocks) * 5, "streamed residual rows");
+    h.s_part.alloc(size_t(2) * kSBlocks * 5, "streamed residual rows");
+    h.s_xs2.alloc(size_t(nloc), "streamed x_s, second buffer");
+    h.s_lam2.alloc(size_t(nloc), "streamed lambda, second buffer");
     h.s_x2.alloc(size_t(2) * lp.n, "streamed x halves");
     h.s_ctrl.alloc(2, "streamed control");
     if (!h.s_hctrl)
@@ -483,17 +500,23 @@ void stream_solve(ldopf_problem& h) {
     hipStream_t s = h.stream;
     hipLaunchKernelGGL(stream_init_kernel, dim3(1), dim3(64), 0, s, a);
     hip_check(hipGetLastError(), "streamed sweep init");
-    const unsigned gblocks = unsigned((a.n + 255) / 256);
     const int rows = int(std::min<int64_t>(kSBlocks, std::max<int64_t>(1, (a.n_groups + kSWaves - 1) / kSWaves)));
     hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
     // node i of a graph computes sweep 32 g + i + 1 (every graph starts after
-    // a multiple of kSGraph sweeps, an even number): its x half is (i + 1) % 2
+    // a multiple of kSGraph sweeps, an even number): it writes buffer
+    // (i + 1) % 2 (x half, x_s, lambda, block sums) and reads the other
     for (int i = 0; i < kSGraph; ++i) {
         StreamArgs ai = a;
-        ai.x = a.x + int64_t((i + 1) % 2) * a.n;
-        hipLaunchKernelGGL(stream_global_kernel, dim3(gblocks + 1), dim3(256), 0, s, ai, rows);
-        void* args[] = {&ai};
-        (void)hipLaunchKernel(local_kernel(h.s_nq), dim3(rows), dim3(64 * kSWaves), args, 0, s);
+        const int wb = (i + 1) % 2;
+        ai.x = a.x + int64_t(wb) * a.n;
+        ai.xs_rd = wb ? a.xs_rd : a.xs_wr;
+        ai.lam_rd = wb ? a.lam_rd : a.lam_wr;
+        ai.xs_wr = wb ? a.xs_wr : const_cast<double*>(a.xs_rd);
+        ai.lam_wr = wb ? a.lam_wr : const_cast<double*>(a.lam_rd);
+        ai.part_rd = wb ? a.part_rd : a.part_wr;
+        ai.part_wr = wb ? a.part_wr : const_cast<double*>(a.part_rd);
+        void* args[] = {&ai, const_cast<int*>(&rows)};
+        (void)hipLaunchKernel(sweep_kernel_for(h.s_nq), dim3(rows + 1), dim3(64 * kSWaves), args, 0, s);
     }
     hip_check(hipStreamEndCapture(s, &h.s_graph), "graph capture");
     hip_check(hipGraphInstantiate(&h.s_exec, h.s_graph, nullptr, nullptr, 0), "graph instantiate");
@@ -521,11 +544,16 @@ void stream_solve(ldopf_problem& h) {
         before = t;
         b ^= 1;
     }
-    // the x of the returned sweep (the sweep number when stopped) into the
-    // handle's x, after the graph queued last
+    // the state of the returned sweep (the sweep number when stopped) into
+    // the handle's x (and x_s, lambda when the sweep is odd), after the graph
+    // queued last
     if (t >= 1)
         hip_check(hipMemcpyAsync(h.x.p, h.s_x2.p + (t % 2) * a.n, size_t(a.n) * 8, hipMemcpyDeviceToDevice, s),
                   "copy x");
+    if (t % 2 == 1) {
+        hip_check(hipMemcpyAsync(h.xs.p, h.s_xs2.p, size_t(a.nloc) * 8, hipMemcpyDeviceToDevice, s), "copy x_s");
+        hip_check(hipMemcpyAsync(h.lam.p, h.s_lam2.p, size_t(a.nloc) * 8, hipMemcpyDeviceToDevice, s), "copy lambda");
+    }
 }
 
 }  // namespace ldopf
