@@ -118,11 +118,10 @@ typedef enum ldopf_sweep_path {
      * fit */
     LDOPF_PATH_PERSISTENT = 1,
     /* the streamed sweep: the same steps of Algorithm 1 with the operators
-     * and state in HBM, two launches per sweep (global update, beside it
-     * the test of the previous sweep on the residual sums of its blocks in a
-     * fixed order; local and dual update with the residual sums of each
-     * block), captured in HIP graphs and replayed by the host until the test
-     * holds. FP64 only, literal residual form and fixed rho;
+     * and state in HBM, one launch per sweep (global, local and dual update
+     * with the residual sums of each block, and beside them the test of the
+     * previous sweep on those sums in a fixed order), captured in HIP graphs
+     * and replayed by the host until the test holds. FP64 only, literal residual form and fixed rho;
      * not for ldopf_solve_noalloc, ldopf_solve_many or the server (those
      * calls return LDOPF_UNSUPPORTED for such a problem) */
     LDOPF_PATH_STREAMED = 2

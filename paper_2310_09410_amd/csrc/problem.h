@@ -65,7 +65,7 @@ struct ldopf_problem {
     DevBuf<int64_t> s_meta, s_ctrl;
     DevBuf<int32_t> s_gidx, s_var_off, s_var_copy, s_groups;
     DevBuf<int4> s_ell;  // the first four copies of each variable
-    DevBuf<double> s_part, s_x2, s_xs2, s_lam2;
+    DevBuf<double> s_part, s_x2, s_u2, s_lam2;
     hipGraph_t s_graph = nullptr;
     hipGraphExec_t s_exec = nullptr;
     int64_t* s_hctrl = nullptr;                 // pinned: the control words after two graphs
@@ -75,7 +75,7 @@ struct ldopf_problem {
     // serving runtime's slot streams, which outlive their problems)
     void use_stream_ordered_memory(hipStream_t s) {
         for (DevBuf<double>* q : {&A, &b, &basis, &abar, &bbar, &c, &lo, &hi, &cnt, &xs, &lam, &x, &hist, &rpart, &gpart,
-                                  &prof, &rholog, &bagg, &s_part, &s_x2, &s_xs2, &s_lam2})
+                                  &prof, &rholog, &bagg, &s_part, &s_x2, &s_u2, &s_lam2})
             q->ordered = s;
         for (DevBuf<int32_t>* q : {&ns, &ms, &rank_d, &flags, &row_canon, &var_gid, &var_slot, &var_slot_lo, &var_slot_hi,
                                    &s_gidx, &s_var_off, &s_var_copy, &s_groups})

@@ -56,9 +56,9 @@ struct StreamArgs {
     const double* hi;
     const double* cnt;
     double* x;              // the half of the two-part x buffer this sweep writes
-    const double* xs_rd;    // x_s and lambda of the previous sweep
+    const double* u_rd;     // u = x_s - lambda / rho and lambda of the previous sweep
     const double* lam_rd;
-    double* xs_wr;          // x_s and lambda of this sweep (sweep k in buffer k % 2)
+    double* u_wr;           // u and lambda of this sweep (sweep k in buffer k % 2)
     double* lam_wr;
     const double* part_rd;  // block sums of the previous sweep [kSBlocks][5], tested here
     double* part_wr;        // block sums of this sweep
@@ -175,35 +175,39 @@ __device__ void stream_test(const StreamArgs& a, int rows) {
         a.ctrl[0] = t + 1;
 }
 
-// closed_1 for variable v: x_v = clip((sum_c x_s,c - (c_v + sum_c lambda_c) /
-// rho) / N_v) over the copies c of v in the previous sweep, in copy order (a
-// NaN passes the clip); the first four copies come from a padded table, so
-// that their loads are in flight together, further ones from the CSR list.
+// closed_1 for variable v: x_v = clip((sum_c u_c - c_v / rho) / N_v) over
+// the copies c of v in the previous sweep, u = x_s - lambda / rho, in copy
+// order (a NaN passes the clip); the first four copies come from a padded
+// table, so that their loads are in flight together, further ones from the
+// CSR list.
 __device__ inline double global_x(const StreamArgs& a, int v) {
     const int4 e = a.ell[v];
     const int q0 = a.var_off[v], q1 = a.var_off[v + 1];
     const int ec[4] = {e.x, e.y, e.z, e.w};
-    double xs4[4], lm4[4];
+    double u4[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        xs4[i] = ec[i] >= 0 ? a.xs_rd[ec[i]] : 0.0;
-        lm4[i] = ec[i] >= 0 ? a.lam_rd[ec[i]] : 0.0;
-    }
-    double sx = 0.0, sl = 0.0;
+    for (int i = 0; i < 4; ++i) u4[i] = ec[i] >= 0 ? a.u_rd[ec[i]] : 0.0;
+    double su = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        if (q0 + i < q1) {
-            sx += xs4[i];
-            sl += lm4[i];
-        }
-    for (int q = q0 + 4; q < q1; ++q) {
-        const int c = a.var_copy[q];
-        sx += a.xs_rd[c];
-        sl += a.lam_rd[c];
-    }
-    const double xh = (sx - (a.c[v] + sl) / a.rho) / a.cnt[v];
+        if (q0 + i < q1) su += u4[i];
+    for (int q = q0 + 4; q < q1; ++q) su += a.u_rd[a.var_copy[q]];
+    const double xh = (su - a.c[v] / a.rho) / a.cnt[v];
     const double lo = a.lo[v], hi = a.hi[v];
     return xh < lo ? lo : (xh > hi ? hi : xh);
+}
+
+// u = x_s - lambda / rho of every copy, before the first sweep (from the
+// handle's x_s and lambda: the initial point or a warm start)
+__global__ void stream_u_kernel(StreamArgs a, const double* xs, const double* lam) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c < a.nloc) a.u_wr[c] = xs[c] - lam[c] * (1.0 / a.rho);
+}
+
+// x_s = u + lambda / rho of the returned sweep, into the handle's x_s
+__global__ void stream_xs_kernel(StreamArgs a, double* xs) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c < a.nloc) xs[c] = a.u_rd[c] + a.lam_rd[c] * (1.0 / a.rho);
 }
 
 // One sweep: closed_1 for each row's variable, closed_2, ADMM-3 and the
@@ -256,7 +260,7 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_sweep_kernel(StreamArgs a
                 z[q] = global_x(a, var);
                 a.x[var] = z[q];
                 l[q] = a.lam_rd[c];
-                xo[q] = a.xs_rd[c];
+                xo[q] = a.u_rd[c] + l[q] * irho;  // x_s of the previous sweep
                 v[q] = z[q] + l[q] * irho;
             }
         }
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_sweep_kernel(StreamArgs a
                 const int64_t c = row0 + j;
                 const double y = a.bbar[c] + (mode ? v[q] - acc[q] : acc[q]);
                 const double l1 = l[q] + rho * (z[q] - y);
-                a.xs_wr[c] = y;
+                a.u_wr[c] = y - l1 * irho;
                 a.lam_wr[c] = l1;
                 const double dz = z[q] - y, dx = y - xo[q];
                 p[0] += dz * dz;
@@ -368,12 +372,13 @@ StreamArgs stream_args(ldopf_problem& h) {
     a.lo = h.lo.p;
     a.hi = h.hi.p;
     a.cnt = h.cnt.p;
-    // sweep k reads buffer (k - 1) % 2 and writes buffer k % 2; buffer 0 is
-    // the handle's x_s and lambda (the initial point or a warm start)
+    // sweep k reads buffer (k - 1) % 2 and writes buffer k % 2; lambda's
+    // buffer 0 is the handle's lambda, u's is filled from the handle's x_s
+    // and lambda (the initial point or a warm start) before the first sweep
     a.x = h.s_x2.p;
-    a.xs_rd = h.xs.p;
+    a.u_rd = h.s_u2.p;
     a.lam_rd = h.lam.p;
-    a.xs_wr = h.s_xs2.p;
+    a.u_wr = h.s_u2.p + h.lp.gidx.size();
     a.lam_wr = h.s_lam2.p;
     a.part_rd = h.s_part.p;
     a.part_wr = h.s_part.p + size_t(kSBlocks) * 5;
@@ -475,7 +480,7 @@ void stream_prepare(ldopf_problem& h) {
     }
     h.s_ell.upload(ell, s, "upload streamed plan");
     h.s_part.alloc(size_t(2) * kSBlocks * 5, "streamed residual rows");
-    h.s_xs2.alloc(size_t(nloc), "streamed x_s, second buffer");
+    h.s_u2.alloc(size_t(2) * nloc, "streamed x_s - lambda / rho, two buffers");
     h.s_lam2.alloc(size_t(nloc), "streamed lambda, second buffer");
     h.s_x2.alloc(size_t(2) * lp.n, "streamed x halves");
     h.s_ctrl.alloc(2, "streamed control");
@@ -500,6 +505,14 @@ void stream_solve(ldopf_problem& h) {
     hipStream_t s = h.stream;
     hipLaunchKernelGGL(stream_init_kernel, dim3(1), dim3(64), 0, s, a);
     hip_check(hipGetLastError(), "streamed sweep init");
+    const unsigned cblocks = unsigned((a.nloc + 255) / 256);
+    if (cblocks > 0) {
+        // buffer 0 holds u of the starting point
+        StreamArgs a0 = a;
+        a0.u_wr = const_cast<double*>(a.u_rd);
+        hipLaunchKernelGGL(stream_u_kernel, dim3(cblocks), dim3(256), 0, s, a0, h.xs.p, h.lam.p);
+        hip_check(hipGetLastError(), "streamed sweep init");
+    }
     const int rows = int(std::min<int64_t>(kSBlocks, std::max<int64_t>(1, (a.n_groups + kSWaves - 1) / kSWaves)));
     hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
     // node i of a graph computes sweep 32 g + i + 1 (every graph starts after
@@ -509,9 +522,9 @@ void stream_solve(ldopf_problem& h) {
         StreamArgs ai = a;
         const int wb = (i + 1) % 2;
         ai.x = a.x + int64_t(wb) * a.n;
-        ai.xs_rd = wb ? a.xs_rd : a.xs_wr;
+        ai.u_rd = wb ? a.u_rd : a.u_wr;
         ai.lam_rd = wb ? a.lam_rd : a.lam_wr;
-        ai.xs_wr = wb ? a.xs_wr : const_cast<double*>(a.xs_rd);
+        ai.u_wr = wb ? a.u_wr : const_cast<double*>(a.u_rd);
         ai.lam_wr = wb ? a.lam_wr : const_cast<double*>(a.lam_rd);
         ai.part_rd = wb ? a.part_rd : a.part_wr;
         ai.part_wr = wb ? a.part_wr : const_cast<double*>(a.part_rd);
@@ -545,14 +558,19 @@ void stream_solve(ldopf_problem& h) {
         b ^= 1;
     }
     // the state of the returned sweep (the sweep number when stopped) into
-    // the handle's x (and x_s, lambda when the sweep is odd), after the graph
+    // the handle's x, x_s (from u and lambda) and lambda, after the graph
     // queued last
     if (t >= 1)
         hip_check(hipMemcpyAsync(h.x.p, h.s_x2.p + (t % 2) * a.n, size_t(a.n) * 8, hipMemcpyDeviceToDevice, s),
                   "copy x");
-    if (t % 2 == 1) {
-        hip_check(hipMemcpyAsync(h.xs.p, h.s_xs2.p, size_t(a.nloc) * 8, hipMemcpyDeviceToDevice, s), "copy x_s");
-        hip_check(hipMemcpyAsync(h.lam.p, h.s_lam2.p, size_t(a.nloc) * 8, hipMemcpyDeviceToDevice, s), "copy lambda");
+    if (t >= 1 && cblocks > 0) {
+        StreamArgs af = a;
+        af.u_rd = t % 2 ? a.u_wr : a.u_rd;
+        af.lam_rd = t % 2 ? a.lam_wr : a.lam_rd;
+        hipLaunchKernelGGL(stream_xs_kernel, dim3(cblocks), dim3(256), 0, s, af, h.xs.p);
+        hip_check(hipGetLastError(), "streamed x_s");
+        if (t % 2 == 1)
+            hip_check(hipMemcpyAsync(h.lam.p, h.s_lam2.p, size_t(a.nloc) * 8, hipMemcpyDeviceToDevice, s), "copy lambda");
     }
 }
 

@@ -1,5 +1,5 @@
-"""GPU parity of the streamed sweep (operators and state in HBM, two
-launches per sweep, graphs replayed by the host) against the FP64 oracle.
+"""GPU parity of the streamed sweep (operators and state in HBM, one launch
+per sweep, graphs replayed by the host) against the FP64 oracle.
 
 The streamed sweep is the path for problems whose operators and state do not
 fit the LDS of one workgroup per CU. It computes the same steps as the
@@ -124,7 +124,10 @@ def test_streamed_mid_size_subsystems(gpu):
 
 
 def test_warm_start_streamed(gpu):
-    """150 sweeps == 60 sweeps, fetch, warm start, 90 sweeps (bit for bit)."""
+    """150 sweeps == 60 sweeps, fetch, warm start, 90 sweeps. The streamed
+    sweep keeps u = x_s - lambda / rho per copy and returns x_s = u + lambda /
+    rho, so a warm start from the returned x_s forms u again up to one
+    rounding: the two runs agree to 1e-13 (on this feeder bit for bit)."""
     P = gpu
     net = feeder("123")
     a = P.ldopf_create(net, _streamed(P, max_iter=150, check_termination=0))
@@ -137,7 +140,7 @@ def test_warm_start_streamed(gpu):
     c.warm_start(xs_m, lam_m)
     c.solve()
     xs_c, lam_c = c.get_local()
-    assert np.array_equal(xs_a, xs_c) and np.array_equal(lam_a, lam_c)
+    assert rel_err(xs_c, xs_a) <= 1e-13 and rel_err(lam_c, lam_a) <= 1e-13
 
 
 def test_too_large_for_the_persistent_sweep(gpu):
