@@ -56,13 +56,13 @@ struct ldopf_problem {
     DevBuf<unsigned char> bpart;
     DevBuf<SweepStatus> st;
     // streamed sweep (a problem too large for the persistent sweep's LDS):
-    // per-subsystem words, copies as 32-bit indices, the copies of each
-    // variable (CSR, and the first four padded), the blocks' residual rows,
-    // control words, the graph
+    // groups of subsystems with their words, copies as 32-bit indices, the
+    // copies of each variable (CSR, and the first four padded), the blocks'
+    // residual rows, control words, the graph
     bool streamed = false;
     int32_t s_nq = 1;
     int64_t s_n_groups = 0;
-    DevBuf<int64_t> s_meta, s_ctrl;
+    DevBuf<int64_t> s_ctrl;
     DevBuf<int32_t> s_gidx, s_var_off, s_var_copy, s_groups;
     DevBuf<int4> s_ell;  // the first four copies of each variable
     DevBuf<double> s_part, s_x2, s_u2, s_lam2;
@@ -80,7 +80,7 @@ struct ldopf_problem {
         for (DevBuf<int32_t>* q : {&ns, &ms, &rank_d, &flags, &row_canon, &var_gid, &var_slot, &var_slot_lo, &var_slot_hi,
                                    &s_gidx, &s_var_off, &s_var_copy, &s_groups})
             q->ordered = s;
-        for (DevBuf<int64_t>* q : {&a_off, &row_off, &loc_off, &basis_off, &s_meta, &s_ctrl}) q->ordered = s;
+        for (DevBuf<int64_t>* q : {&a_off, &row_off, &loc_off, &basis_off, &s_ctrl}) q->ordered = s;
         for (DevBuf<uint16_t>* q : {&row_lvar, &row_sub, &var_copy_off, &var_copy_rows, &tk_sub}) q->ordered = s;
         parts.ordered = s;
         subs.ordered = s;

@@ -39,11 +39,14 @@ namespace {
 constexpr int kSWaves = 8;    // waves per block
 constexpr int kSBlocks = 1024; // blocks of subsystem groups per launch: rows of partial sums
 constexpr int kSGraph = 32;   // sweeps per captured graph
+constexpr int kGroupWords = 20;  // words per group record
 
 struct StreamArgs {
     int64_t S, n, nloc;
-    const int64_t* meta;  // per subsystem: n_s | K_s << 16 | mode << 32, first copy, offset of W in the basis
-    const int32_t* groups;  // per group of subsystems: lanes each, count, largest K_s, 0, then up to 4 subsystems
+    // per group of subsystems (kGroupWords words): lanes each, count, largest
+    // K_s, 0, then per slot (up to 4) n_s | K_s << 12 | mode << 24, its first
+    // copy, and the offset of its K_s rows in the basis (two words)
+    const int32_t* groups;
     int64_t n_groups;
     const int32_t* gidx;
     const int32_t* var_off;
@@ -233,22 +236,24 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_sweep_kernel(StreamArgs a
     const int64_t blk = int64_t(blockIdx.x) - 1, nblk = int64_t(gridDim.x) - 1;
     const double rho = a.rho, irho = 1.0 / a.rho;
     double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t g = blk * kSWaves + wv; g < a.n_groups; g += nblk * kSWaves) {
-        const int32_t* gr = a.groups + 8 * g;
+    for (int64_t g = blk * kSWaves + __builtin_amdgcn_readfirstlane(wv); g < a.n_groups; g += nblk * kSWaves) {
+        // the group record is the same for the whole wave (scalar loads); a
+        // lane takes its slot's words from it
+        const int32_t* gr = a.groups + kGroupWords * g;
         const int G = gr[0], count = gr[1], kmax = gr[2];
         const int slot = lane / G, jl = lane - slot * G;
-        const int sub = slot < count ? gr[4 + slot] : -1;
-        int n = 0, K = 0, mode = 0;
-        int64_t row0 = 0;
-        const double* W = a.basis;
-        if (sub >= 0) {
-            const int64_t m0 = a.meta[3 * int64_t(sub)];
-            n = int(m0 & 0xffff);
-            K = int((m0 >> 16) & 0xffff);
-            mode = int((m0 >> 32) & 1);
-            row0 = a.meta[3 * int64_t(sub) + 1];
-            W = a.basis + a.meta[3 * int64_t(sub) + 2];
-        }
+        int nkm = 0, r0 = 0, wlo = 0, whi = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (slot == i && i < count) {
+                nkm = gr[4 + 4 * i];
+                r0 = gr[5 + 4 * i];
+                wlo = gr[6 + 4 * i];
+                whi = gr[7 + 4 * i];
+            }
+        const int n = nkm & 0xfff, K = (nkm >> 12) & 0xfff, mode = (nkm >> 24) & 1;
+        const int64_t row0 = r0;
+        const double* W = a.basis + ((int64_t(whi) << 32) | uint32_t(wlo));
         double z[NQ], l[NQ], xo[NQ], v[NQ], acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -359,7 +364,6 @@ StreamArgs stream_args(ldopf_problem& h) {
     a.S = h.lp.S;
     a.n = h.lp.n;
     a.nloc = int64_t(h.lp.gidx.size());
-    a.meta = h.s_meta.p;
     a.groups = h.s_groups.p;
     a.n_groups = h.s_n_groups;
     a.gidx = h.s_gidx.p;
@@ -450,8 +454,20 @@ void stream_prepare(ldopf_problem& h) {
     auto add_group = [&](int32_t G, const std::vector<int32_t>& subs) {
         int32_t kmax = 0;
         for (int32_t q : subs) kmax = std::max<int32_t>(kmax, int32_t((meta[3 * size_t(q)] >> 16) & 0xffff));
-        groups.insert(groups.end(), {G, int32_t(subs.size()), kmax, 0, -1, -1, -1, -1});
-        for (size_t i = 0; i < subs.size(); ++i) groups[groups.size() - 4 + i] = subs[i];
+        const size_t at = groups.size();
+        groups.resize(at + kGroupWords, 0);
+        groups[at] = G;
+        groups[at + 1] = int32_t(subs.size());
+        groups[at + 2] = kmax;
+        for (size_t i = 0; i < subs.size(); ++i) {
+            const int64_t q = subs[i], m0 = meta[3 * size_t(q)];
+            const int64_t n = m0 & 0xffff, K = (m0 >> 16) & 0xffff, mode = (m0 >> 32) & 1;
+            const int64_t woff = meta[3 * size_t(q) + 2];
+            groups[at + 4 + 4 * i] = int32_t(n | (K << 12) | (mode << 24));
+            groups[at + 5 + 4 * i] = int32_t(meta[3 * size_t(q) + 1]);
+            groups[at + 6 + 4 * i] = int32_t(uint32_t(uint64_t(woff) & 0xffffffffu));
+            groups[at + 7 + 4 * i] = int32_t(uint32_t(uint64_t(woff) >> 32));
+        }
         ++n_groups;
     };
     std::vector<int32_t> s16, s32, s64;
@@ -466,7 +482,6 @@ void stream_prepare(ldopf_problem& h) {
         add_group(32, std::vector<int32_t>(s32.begin() + i, s32.begin() + std::min(s32.size(), i + 2)));
     for (size_t i = 0; i < s16.size(); i += 4)
         add_group(16, std::vector<int32_t>(s16.begin() + i, s16.begin() + std::min(s16.size(), i + 4)));
-    h.s_meta.upload(meta, s, "upload streamed plan");
     h.s_groups.upload(groups, s, "upload streamed plan");
     h.s_n_groups = n_groups;
     h.s_gidx.upload(g32, s, "upload streamed plan");
