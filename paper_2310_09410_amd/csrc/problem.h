@@ -65,6 +65,7 @@ struct ldopf_problem {
     DevBuf<int64_t> s_ctrl;
     DevBuf<int32_t> s_gidx, s_var_off, s_var_copy, s_groups;
     DevBuf<int4> s_ell;  // the first four copies of each variable
+    DevBuf<double4> s_vconst;  // each variable's c, bounds and copy count
     DevBuf<double> s_part, s_x2, s_u2, s_lam2;
     hipGraph_t s_graph = nullptr;
     hipGraphExec_t s_exec = nullptr;
@@ -85,6 +86,7 @@ struct ldopf_problem {
         parts.ordered = s;
         subs.ordered = s;
         s_ell.ordered = s;
+        s_vconst.ordered = s;
         var_writer.ordered = s;
         bpart.ordered = s;
         st.ordered = s;

@@ -54,10 +54,7 @@ struct StreamArgs {
     const int4* ell;  // per variable its first four copies, -1 padded
     const double* basis;
     const double* bbar;
-    const double* c;
-    const double* lo;
-    const double* hi;
-    const double* cnt;
+    const double4* vconst;  // per variable: c, lower bound, upper bound, copy count
     double* x;              // the half of the two-part x buffer this sweep writes
     const double* u_rd;     // u = x_s - lambda / rho and lambda of the previous sweep
     const double* lam_rd;
@@ -183,8 +180,9 @@ __device__ void stream_test(const StreamArgs& a, int rows) {
 // order (a NaN passes the clip); the first four copies come from a padded
 // table, so that their loads are in flight together, further ones from the
 // CSR list.
-__device__ inline double global_x(const StreamArgs& a, int v) {
+__device__ inline double global_x(const StreamArgs& a, int v, int* first) {
     const int4 e = a.ell[v];
+    *first = e.x;
     const int q0 = a.var_off[v], q1 = a.var_off[v + 1];
     const int ec[4] = {e.x, e.y, e.z, e.w};
     double u4[4];
@@ -195,9 +193,9 @@ __device__ inline double global_x(const StreamArgs& a, int v) {
     for (int i = 0; i < 4; ++i)
         if (q0 + i < q1) su += u4[i];
     for (int q = q0 + 4; q < q1; ++q) su += a.u_rd[a.var_copy[q]];
-    const double xh = (su - a.c[v] / a.rho) / a.cnt[v];
-    const double lo = a.lo[v], hi = a.hi[v];
-    return xh < lo ? lo : (xh > hi ? hi : xh);
+    const double4 k = a.vconst[v];
+    const double xh = (su - k.x / a.rho) / k.w;
+    return xh < k.y ? k.y : (xh > k.z ? k.z : xh);
 }
 
 // u = x_s - lambda / rho of every copy, before the first sweep (from the
@@ -262,8 +260,9 @@ __global__ __launch_bounds__(64 * kSWaves) void stream_sweep_kernel(StreamArgs a
             if (j < n) {
                 const int64_t c = row0 + j;
                 const int var = a.gidx[c];
-                z[q] = global_x(a, var);
-                a.x[var] = z[q];
+                int first;
+                z[q] = global_x(a, var, &first);
+                if (first == c) a.x[var] = z[q];  // written once, by the variable's first copy
                 l[q] = a.lam_rd[c];
                 xo[q] = a.u_rd[c] + l[q] * irho;  // x_s of the previous sweep
                 v[q] = z[q] + l[q] * irho;
@@ -372,10 +371,7 @@ StreamArgs stream_args(ldopf_problem& h) {
     a.ell = h.s_ell.p;
     a.basis = h.basis.p;
     a.bbar = h.bbar.p;
-    a.c = h.c.p;
-    a.lo = h.lo.p;
-    a.hi = h.hi.p;
-    a.cnt = h.cnt.p;
+    a.vconst = h.s_vconst.p;
     // sweep k reads buffer (k - 1) % 2 and writes buffer k % 2; lambda's
     // buffer 0 is the handle's lambda, u's is filled from the handle's x_s
     // and lambda (the initial point or a warm start) before the first sweep
@@ -494,6 +490,10 @@ void stream_prepare(ldopf_problem& h) {
         ell[v] = int4{e[0], e[1], e[2], e[3]};
     }
     h.s_ell.upload(ell, s, "upload streamed plan");
+    std::vector<double4> vconst(lp.n);
+    for (int64_t v = 0; v < lp.n; ++v)
+        vconst[v] = double4{lp.c[v], lp.lo[v], lp.hi[v], double(var_off[v + 1] - var_off[v])};
+    h.s_vconst.upload(vconst, s, "upload streamed plan");
     h.s_part.alloc(size_t(2) * kSBlocks * 5, "streamed residual rows");
     h.s_u2.alloc(size_t(2) * nloc, "streamed x_s - lambda / rho, two buffers");
     h.s_lam2.alloc(size_t(nloc), "streamed lambda, second buffer");
