@@ -432,7 +432,9 @@ LDOPF_API int ldopf_batch_reset(ldopf_batch* h);
 LDOPF_API int ldopf_batch_solve(ldopf_batch* h, ldopf_batch_status* status);
 /* One scenario's iterations (its stopping sweep), converged flag and last residuals. */
 LDOPF_API int ldopf_batch_get_scenario(const ldopf_batch* h, int32_t scen, ldopf_status* status);
-/* One scenario's global x [n] and local x_s, lambda [N_loc] (either nullable), as FP64. */
+/* One scenario's global x [n] and local x_s, lambda [N_loc] (either nullable), as FP64,
+ * of its returned sweep. The batch keeps lambda and x_s - lambda / rho per copy in FP32;
+ * x_s is formed from the two as the sweep forms it. */
 LDOPF_API int ldopf_batch_get_global(const ldopf_batch* h, int32_t scen, double* x, int64_t cap);
 LDOPF_API int ldopf_batch_get_local(const ldopf_batch* h, int32_t scen, double* xs, double* lam, int64_t cap);
 LDOPF_API int ldopf_batch_get_sizes(const ldopf_batch* h, ldopf_batch_sizes* out);
