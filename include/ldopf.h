@@ -121,7 +121,9 @@ typedef enum ldopf_sweep_path {
      * and state in HBM, one launch per sweep (global, local and dual update
      * with the residual sums of each block, and beside them the test of the
      * previous sweep on those sums in a fixed order), captured in HIP graphs
-     * and replayed by the host until the test holds. FP64 only, literal residual form and fixed rho;
+     * and replayed by the host until the test holds. It keeps lambda and
+     * x_s - lambda / rho per copy; the x_s it returns is formed from the two
+     * (a warm start from it reproduces the state up to one rounding). FP64 only, literal residual form and fixed rho;
      * not for ldopf_solve_noalloc, ldopf_solve_many or the server (those
      * calls return LDOPF_UNSUPPORTED for such a problem) */
     LDOPF_PATH_STREAMED = 2
