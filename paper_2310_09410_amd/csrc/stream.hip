@@ -36,8 +36,8 @@ namespace ldopf {
 
 namespace {
 
-constexpr int kSWaves = 8;    // waves per block
-constexpr int kSBlocks = 1024; // blocks of subsystem groups per launch: rows of partial sums
+constexpr int kSWaves = 4;    // waves per block
+constexpr int kSBlocks = 2048; // blocks of subsystem groups per launch: rows of partial sums
 constexpr int kSGraph = 32;   // sweeps per captured graph
 constexpr int kGroupWords = 20;  // words per group record
 
