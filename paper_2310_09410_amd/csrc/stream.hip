@@ -119,7 +119,7 @@ __global__ void stream_init_kernel(StreamArgs a) {
 
 // Block 0 of a launch: the test of the sweep the previous launch computed
 // (its blocks' residual rows in a fixed order: thread r takes rows r,
-// r + 512, ..., then sums over each wave and the waves in order), its
+// r + 64 kSWaves, ..., then sums over each wave and the waves in order), its
 // history row and status; then either the stop or the next sweep's number.
 // Every thread of the block calls it.
 __device__ void stream_test(const StreamArgs& a, int rows) {
@@ -215,8 +215,9 @@ __global__ void stream_xs_kernel(StreamArgs a, double* xs) {
 // residual sums. A wave takes one group of subsystems at a time: four of at
 // most 16 variables (16 lanes each), two of at most 32, or one (64 lanes, NQ
 // rows per lane, n_s <= 64 NQ); a lane holds row j of its subsystem, forms
-// x of the row's variable (each copy's lane forms the same bits, and writes
-// them), and t_k is a sum over the subsystem's lanes. Operator rows are
+// x of the row's variable (each copy's lane forms the same bits; the lane of
+// the variable's first copy writes them), and t_k is a sum over the
+// subsystem's lanes. Operator rows are
 // loaded kKB at a time (fewer for more rows per lane, so that the batch
 // stays in registers). Block 0 runs the test of the previous sweep instead;
 // a block that sees the stop it decides skips its groups, which only spares
